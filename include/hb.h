@@ -1,0 +1,187 @@
+/*
+ * hb.h - C interface of the MI355X harmonic-balance (HB) GLS Navier-Stokes
+ * library: residual, Jacobian-vector product and Newton-GMRES solve of the
+ * time-periodic incompressible Navier-Stokes equations on P1-P1 tetrahedra.
+ *
+ * The method is that of Jia & Esmaily, "Introducing a harmonic balance
+ * Navier-Stokes finite element solver to accelerate cardiovascular
+ * simulations" (arXiv 2411.14315):
+ *   - problem statement: Section 2.1, eq. NS-time (rigid walls, Dirichlet
+ *     data g on inlets and walls, normal traction h on outlets);
+ *   - harmonic balance form: Section 2.1, eqs. upghdft and NS-harm
+ *     (N = 2K+1 time samples, H = E^-1 Omega E);
+ *   - GLS weak form and tau: Section 2.2, eqs. NS-weak and tau;
+ *   - discrete residual: Section 2.3, eq. Rmc; backflow stabilisation
+ *     (beta = 0.2) on outlets, Section 2.3;
+ *   - Newton-Raphson with pseudo time stepping and Jacobi-preconditioned
+ *     GMRES: Section 2.3, eqs. NR, splitK, ptangent, K_mat, ctangent.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Modal layout.  A nodal field set Y is an array of doubles
+ *     Y[f][m][a],  f in {u1, u2, u3, p},  m in 0..2K,  a = node (contiguous)
+ * with harmonic order [a_0, a_1, b_1, ..., a_K, b_K], meaning that at time t
+ *     q(t) = a_0 + sum_{m=1..K} a_m cos(m w t) + b_m sin(m w t),  w = 2 pi/T.
+ * The paper's complex coefficient is q*_m = (a_m - i b_m)/2.  Time samples are
+ * t_n = n T / N, n = 0..N-1.  Residual and Jacobian-vector outputs use the
+ * same layout and hold the real DFT of the time-sample rows of eq. Rmc:
+ *     R[f][0][a] = (1/N) sum_n r_n,  R[f][2m-1][a] = (2/N) sum_n r_n cos(2 pi m n/N),
+ *     R[f][2m][a] = (2/N) sum_n r_n sin(2 pi m n/N).
+ *
+ * Dirichlet nodes are the nodes of wall and inlet faces.  Y's velocity entries
+ * there are ignored on input and replaced by the boundary data; the momentum
+ * rows of R and JV there are zero; V's velocity entries there are taken as 0.
+ * Continuity rows exist at every node (eq. Rmc).
+ *
+ * Memory.  Arrays documented "device" are caller-owned device allocations
+ * (for example torch tensors) on the current HIP device; "host" arrays are
+ * read during the call only.  The library owns what hb_mesh_create
+ * allocates.  A handle must not be used by two calls at the same time;
+ * calls on one handle are ordered by their stream.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  hb_residual, hb_jvp and hb_jacobi are asynchronous on it;
+ * hb_newton_solve returns after its work has finished.
+ *
+ * Errors.  Every call returns HB_OK (0) or a negative status; nothing throws
+ * across the interface.  hb_last_error() returns a thread-local message for
+ * the last failure on the calling thread.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HB_OK = 0,
+  HB_ERR_ARG = -1,     /* invalid argument, size or pointer                  */
+  HB_ERR_MESH = -2,    /* index out of range, degenerate tetrahedron, bad face */
+  HB_ERR_DEVICE = -3,  /* HIP runtime or kernel launch failure               */
+  HB_ERR_NOCONV = -4,  /* Newton iteration limit reached before tolerance     */
+  HB_ERR_NAN = -5,     /* non-finite residual                                  */
+  HB_ERR_OOM = -6      /* device allocation failed                            */
+};
+
+/* Boundary group kinds (hb_mesh_create group_kind). */
+enum { HB_WALL = 0, HB_INLET = 1, HB_OUTLET = 2 };
+
+/* hb_jvp flags: tangent kind (bit 0) and vector precision (bit 1). */
+enum {
+  HB_JV_EXACT = 0, /* exact directional derivative of the residual            */
+  HB_JV_PAPER = 1, /* the paper's tangent C + P (eqs. ptangent, K_mat, ctangent):
+                      frozen advection and tau, stabilisation time terms
+                      dropped, no outlet terms                               */
+  HB_F64 = 0,
+  HB_F32 = 2       /* V and JV are float arrays (mixed-precision path)         */
+};
+
+typedef struct hb_mesh hb_mesh;
+
+/* Fluid and discretisation parameters (Section 2.1-2.3). */
+typedef struct {
+  double rho;     /* density > 0                                  */
+  double mu;      /* dynamic viscosity > 0                        */
+  double period;  /* cycle duration T > 0; w = 2 pi / T            */
+  int32_t K;      /* retained harmonics, 0 <= K <= 32; N = 2K+1    */
+  double C_I;     /* tau constant (3 for tetrahedra, eq. tau)      */
+  double beta_bf; /* backflow coefficient (0.2 in the paper)       */
+} hb_params;
+
+/* Boundary data. */
+typedef struct {
+  const double* dirichlet; /* device [3][N][n] modal velocity data; only
+                              Dirichlet nodes are read (walls: zero)        */
+  const double* outlet_h;  /* host [n_outlets][N] modal normal traction h
+                              (h = -p_out for a pressure outlet), or NULL
+                              for zero traction                              */
+  const double* outlet_R;  /* host [n_outlets] resistances, or NULL.  With a
+                              resistance the traction is
+                              h_n = h_given,n - R Q_n,  Q_n = outlet flux at
+                              sample n (a time-local extension; the paper
+                              leaves resistance outlets to future work)       */
+} hb_bc;
+
+/* Create a mesh handle on the current HIP device.
+ *   xyz        host [n_nodes][3] coordinates
+ *   tets       host [n_tets][4] 0-based node indices; negatively oriented
+ *              tetrahedra are re-oriented by swapping local nodes 2 and 3
+ *   faces      host [n_faces][3] boundary triangles (any orientation)
+ *   face_group host [n_faces] group index in 0..n_groups-1
+ *   group_kind host [n_groups] HB_WALL / HB_INLET / HB_OUTLET
+ * Outlet groups are numbered in increasing group index.  Fails with
+ * HB_ERR_MESH for out-of-range indices, |V| < 1e-14 * mean|V|, or a face that
+ * is not a face of any tetrahedron; HB_ERR_ARG without any outlet group
+ * (the pressure would be undetermined).  *out receives the handle. */
+int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets,
+                   int64_t n_faces, const int32_t* faces, const int32_t* face_group,
+                   int32_t n_groups, const int32_t* group_kind, hb_mesh** out);
+
+void hb_mesh_destroy(hb_mesh* mesh);
+
+/* info[0..7] = n_nodes, n_tets, n_dirichlet_nodes, n_outlet_faces,
+ * n_outlets, n_reoriented, n_inlet_nodes, device bytes held. */
+int hb_mesh_info(const hb_mesh* mesh, int64_t* info);
+
+/* R = modal HB residual of eq. Rmc at Y (device [4][N][n] in, out). */
+int hb_residual(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+                double* R, void* stream);
+
+/* JV = dR/dY [V] at Y (device arrays; V and JV double, or float with HB_F32).
+ * Flags: HB_JV_EXACT or HB_JV_PAPER, optionally | HB_F32. */
+int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+           const void* V, void* JV, int32_t flags, void* stream);
+
+/* Jacobi diagonal of the paper's tangent (Section 2.3: diag(P), since C has
+ * a zero diagonal) plus shift * int N_A^2 on the velocity rows, at Y, in time
+ * samples: D device [2][N][n], D[0] = velocity rows (equal for the three
+ * components; 1 at Dirichlet nodes), D[1] = continuity rows. */
+int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+              double shift, double* D, void* stream);
+
+typedef struct {
+  double rtol;       /* stop when ||r||_2 <= rtol * r_ref (default 1e-8)              */
+  double r_ref;      /* reference norm; <= 0 means ||r(Y_in)||_2                     */
+  double gmres_eta;  /* relative linear tolerance (0.03 in the paper)                 */
+  double cfl;        /* initial pseudo step dt = cfl h_c / u_c                         */
+  double c1;         /* pseudo-time constant (1.5 for rho_inf = 0)                    */
+  int32_t restart;   /* GMRES restart length (default 50)                             */
+  int32_t max_newton;
+  int32_t max_gmres; /* per Newton step                                               */
+  int32_t precision; /* HB_F64, or 1 = mixed (FP32 Jv and Krylov basis)               */
+  int32_t jv_kind;   /* HB_JV_EXACT or HB_JV_PAPER for the Krylov operator            */
+  int32_t verbose;   /* print one line per Newton step to stderr                      */
+} hb_solve_opts;
+
+typedef struct {
+  int32_t newton_iters;
+  int32_t gmres_iters;
+  int32_t status;
+  double r0;       /* ||r(Y_in)||_2, time-sample 2-norm  */
+  double r_final;
+  double r_ref;
+  double wall_s;
+  double jv_ms;    /* total time spent in Krylov operator applications */
+  int32_t n_jv;
+} hb_solve_report;
+
+/* Inexact Newton with pseudo-time continuation (Section 2.3): the tangent
+ * receives c1 rho/dt int N_A N_B on velocity rows, dt grows by switched
+ * evolution relaxation; right-Jacobi-preconditioned restarted GMRES with
+ * classical Gram-Schmidt run twice.  Y (device [4][N][n]) holds the initial
+ * guess on entry and the solution on return.  Returns HB_OK on convergence,
+ * HB_ERR_NOCONV with Y = last iterate otherwise; the report is filled in both
+ * cases. */
+int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
+                    const hb_solve_opts* opts, hb_solve_report* report, void* stream);
+
+const char* hb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HB_H */

@@ -1,0 +1,245 @@
+"""Python binding of the MI355X harmonic-balance GLS Navier-Stokes library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libhb.so`` (see include/hb.h for the meaning, layout and
+ownership of each argument).  PyTorch provides device memory and streams.
+The binding raises if the library is missing; it never falls back to
+another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhb.so")
+
+HB_OK, HB_ERR_ARG, HB_ERR_MESH, HB_ERR_DEVICE, HB_ERR_NOCONV, HB_ERR_NAN, HB_ERR_OOM = (
+    0, -1, -2, -3, -4, -5, -6)
+HB_JV_EXACT, HB_JV_PAPER, HB_F64, HB_F32 = 0, 1, 0, 2
+HB_MIXED = 1
+
+
+class HBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hb status {status}: {msg}")
+        self.status = status
+
+
+class _Params(C.Structure):
+    _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("period", C.c_double),
+                ("K", C.c_int32), ("C_I", C.c_double), ("beta_bf", C.c_double)]
+
+
+class _BC(C.Structure):
+    _fields_ = [("dirichlet", C.c_void_p), ("outlet_h", C.c_void_p), ("outlet_R", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("r_ref", C.c_double), ("gmres_eta", C.c_double),
+                ("cfl", C.c_double), ("c1", C.c_double), ("restart", C.c_int32),
+                ("max_newton", C.c_int32), ("max_gmres", C.c_int32), ("precision", C.c_int32),
+                ("jv_kind", C.c_int32), ("verbose", C.c_int32)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("status", C.c_int32),
+                ("r0", C.c_double), ("r_final", C.c_double), ("r_ref", C.c_double),
+                ("wall_s", C.c_double), ("jv_ms", C.c_double), ("n_jv", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhb.so (built by paper_2411_14315_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HBError(HB_ERR_DEVICE, f"{LIB_PATH} is missing: run paper_2411_14315_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.hb_mesh_create.argtypes = [i64, vp, i64, vp, i64, vp, vp, i32, vp, C.POINTER(vp)]
+    lib.hb_mesh_destroy.argtypes = [vp]
+    lib.hb_mesh_destroy.restype = None
+    lib.hb_mesh_info.argtypes = [vp, vp]
+    lib.hb_residual.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, vp, vp]
+    lib.hb_jvp.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, vp, vp, i32, vp]
+    lib.hb_jacobi.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, dbl, vp, vp]
+    lib.hb_newton_solve.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp,
+                                    C.POINTER(_Opts), C.POINTER(_Report), vp]
+    lib.hb_last_error.restype = C.c_char_p
+    for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
+                 "hb_newton_solve"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != HB_OK:
+        raise HBError(status, load().hb_last_error().decode())
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise HBError(HB_ERR_ARG, "expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Mesh:
+    """Owns an hb_mesh handle; built from host arrays."""
+
+    def __init__(self, xyz, tets, faces, face_group, group_kind):
+        lib = load()
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        faces = np.ascontiguousarray(faces, dtype=np.int32)
+        face_group = np.ascontiguousarray(face_group, dtype=np.int32)
+        group_kind = np.ascontiguousarray(group_kind, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib.hb_mesh_create(xyz.shape[0], xyz.ctypes.data, tets.shape[0], tets.ctypes.data,
+                                  faces.shape[0], faces.ctypes.data, face_group.ctypes.data,
+                                  group_kind.shape[0], group_kind.ctypes.data, C.byref(h)))
+        self._h = h
+        self.n_nodes = xyz.shape[0]
+        self.n_outlets = int(np.sum(group_kind == 2))
+
+    @classmethod
+    def from_mesh(cls, m):
+        return cls(m.xyz, m.tets, m.faces, m.face_group, m.group_kind)
+
+    def info(self) -> dict:
+        out = np.zeros(8, np.int64)
+        _check(load().hb_mesh_info(self._h, out.ctypes.data))
+        keys = ("n_nodes", "n_tets", "n_dirichlet", "n_outlet_faces", "n_outlets",
+                "n_reoriented", "n_inlet", "device_bytes")
+        return dict(zip(keys, map(int, out)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hb_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Params:
+    rho: float = 1.06
+    mu: float = 0.04
+    period: float = 1.0
+    K: int = 2
+    C_I: float = 3.0
+    beta_bf: float = 0.2
+
+    @property
+    def N(self):
+        return 2 * self.K + 1
+
+    def _c(self):
+        return _Params(self.rho, self.mu, self.period, self.K, self.C_I, self.beta_bf)
+
+
+class BC:
+    """Boundary data: ``dirichlet`` a device tensor (3, N, n); ``outlet_h``
+    host (n_outlets, N) modal traction or None; ``outlet_R`` host
+    (n_outlets,) or None."""
+
+    def __init__(self, dirichlet, outlet_h=None, outlet_R=None):
+        self.dirichlet = dirichlet
+        self.outlet_h = None if outlet_h is None else np.ascontiguousarray(outlet_h, np.float64)
+        self.outlet_R = None if outlet_R is None else np.ascontiguousarray(outlet_R, np.float64)
+
+    def _c(self):
+        return _BC(_ptr(self.dirichlet),
+                   None if self.outlet_h is None else self.outlet_h.ctypes.data,
+                   None if self.outlet_R is None else self.outlet_R.ctypes.data)
+
+
+def _params(p):
+    if isinstance(p, Params):
+        return p
+    return Params(p.rho, p.mu, p.period, p.K, p.C_I, p.beta_bf)
+
+
+def residual(mesh: Mesh, params, bc: BC, Y, R=None, stream=None):
+    import torch
+    if R is None:
+        R = torch.empty_like(Y)
+    pc, bcc = _params(params)._c(), bc._c()
+    _check(load().hb_residual(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), _ptr(R),
+                              _stream(stream)))
+    return R
+
+
+def jvp(mesh: Mesh, params, bc: BC, Y, V, JV=None, kind: str = "exact", stream=None):
+    import torch
+    if JV is None:
+        JV = torch.empty_like(V)
+    flags = HB_JV_EXACT if kind == "exact" else HB_JV_PAPER
+    if V.dtype == torch.float32:
+        flags |= HB_F32
+    pc, bcc = _params(params)._c(), bc._c()
+    _check(load().hb_jvp(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), _ptr(V), _ptr(JV), flags,
+                         _stream(stream)))
+    return JV
+
+
+def jacobi(mesh: Mesh, params, bc: BC, Y, shift: float = 0.0, D=None, stream=None):
+    import torch
+    p = _params(params)
+    if D is None:
+        D = torch.empty((2, p.N, mesh.n_nodes), dtype=torch.float64, device=Y.device)
+    pc, bcc = p._c(), bc._c()
+    _check(load().hb_jacobi(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), float(shift), _ptr(D),
+                            _stream(stream)))
+    return D
+
+
+@dataclass
+class SolveOptions:
+    rtol: float = 1e-8
+    r_ref: float = 0.0
+    gmres_eta: float = 0.03
+    cfl: float = 1.0
+    c1: float = 1.5
+    restart: int = 50
+    max_newton: int = 50
+    max_gmres: int = 1000
+    precision: int = HB_F64
+    jv_kind: int = HB_JV_EXACT
+    verbose: int = 0
+
+    def _c(self):
+        return _Opts(self.rtol, self.r_ref, self.gmres_eta, self.cfl, self.c1, self.restart,
+                     self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose)
+
+
+def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None,
+                 stream=None, raise_on_noconv: bool = True) -> dict:
+    """Solve in place (Y holds the guess on entry, the solution on return)."""
+    opts = opts or SolveOptions()
+    rep = _Report()
+    pc, bcc, oc = _params(params)._c(), bc._c(), opts._c()
+    st = load().hb_newton_solve(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), C.byref(oc),
+                                C.byref(rep), _stream(stream))
+    out = {k: getattr(rep, k) for k, _ in _Report._fields_}
+    if st != HB_OK and not (st == HB_ERR_NOCONV and not raise_on_noconv):
+        _check(st)
+    return out

@@ -1,0 +1,817 @@
+// Host side of the HB library: mesh handles, argument checking, workspace,
+// the modal residual / Jacobian-vector entry points and the Newton-GMRES
+// driver (Section 2.3 of arXiv 2411.14315).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hb.h"
+#include "hb_internal.h"
+
+using hb::DevMesh;
+using hb::Phys;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HB_CHECK(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(e_ == hipErrorOutOfMemory ? HB_ERR_OOM : HB_ERR_DEVICE,           \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, b ? b : 8);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Buffers that depend on the number of samples N.
+struct Workspace {
+  int N = -1;
+  DevBuf Sy, Sv, acc, tab, small, dg, dinv;
+  std::vector<double> tab_host;
+  std::vector<double> bc_host;  // hs (n_out N) then R (n_out), as last uploaded
+  bool bc_has_R = false;
+  bool bc_valid = false;
+};
+
+}  // namespace
+
+struct hb_mesh {
+  DevMesh dm;
+  DevBuf tets, geo, dmask, of, ofn, oid;
+  int64_t n_dirichlet = 0, n_reoriented = 0, n_inlet = 0;
+  std::vector<int32_t> inlet_nodes;  // inlet nodes that are not wall nodes
+  double mean_vol = 0.0;
+  int device = 0;
+  Workspace ws;
+  size_t bytes_held() const {
+    return tets.bytes + geo.bytes + dmask.bytes + of.bytes + ofn.bytes + oid.bytes + ws.Sy.bytes +
+           ws.Sv.bytes + ws.acc.bytes + ws.tab.bytes + ws.small.bytes + ws.dg.bytes +
+           ws.dinv.bytes;
+  }
+};
+
+namespace {
+
+// Real DFT tables for N = 2K+1 samples t_n = n T/N (Section 2.1,
+// eq. upghdft, in the real [a_0, a_1, b_1, ...] ordering).
+void build_tables(int K, double omega, std::vector<double>& tab) {
+  const int N = 2 * K + 1;
+  const size_t NN = (size_t)N * N;
+  tab.assign(hb::TAB_COUNT * NN, 0.0);
+  double* Binv = tab.data() + hb::TAB_BINV * NN;
+  double* Bder = tab.data() + hb::TAB_BDER * NN;
+  double* Fwd = tab.data() + hb::TAB_FWD * NN;
+  double* FwdD = tab.data() + hb::TAB_FWDD * NN;
+  double* Hs = tab.data() + hb::TAB_H * NN;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int s = 0; s < N; ++s) {
+    Binv[s * N + 0] = 1.0;
+    Fwd[0 * N + s] = 1.0 / N;
+    for (int j = 1; j <= K; ++j) {
+      const double th = two_pi * (double)((j * s) % N) / (double)N;
+      const double c = std::cos(th), sn = std::sin(th);
+      Binv[s * N + 2 * j - 1] = c;
+      Binv[s * N + 2 * j] = sn;
+      Bder[s * N + 2 * j - 1] = -j * omega * sn;
+      Bder[s * N + 2 * j] = j * omega * c;
+      Fwd[(2 * j - 1) * N + s] = 2.0 * c / N;
+      Fwd[(2 * j) * N + s] = 2.0 * sn / N;
+      // D (a_j, b_j) = (j w b_j, -j w a_j)
+      FwdD[(2 * j - 1) * N + s] = j * omega * 2.0 * sn / N;
+      FwdD[(2 * j) * N + s] = -j * omega * 2.0 * c / N;
+    }
+  }
+  for (int s = 0; s < N; ++s)
+    for (int k = 0; k < N; ++k) {
+      double v = 0.0;
+      for (int m = 0; m < N; ++m) v += Bder[s * N + m] * Fwd[m * N + k];
+      Hs[s * N + k] = v;
+    }
+}
+
+int check_params(const hb_params* prm) {
+  if (!prm) return fail(HB_ERR_ARG, "params is NULL");
+  if (!(prm->rho > 0) || !(prm->mu > 0) || !(prm->period > 0))
+    return fail(HB_ERR_ARG, "rho, mu and period must be positive");
+  if (prm->K < 0 || prm->K > 32) return fail(HB_ERR_ARG, "K must be in 0..32");
+  if (!(prm->C_I > 0)) return fail(HB_ERR_ARG, "C_I must be positive");
+  if (!(prm->beta_bf >= 0)) return fail(HB_ERR_ARG, "beta_bf must be >= 0");
+  return HB_OK;
+}
+
+Phys make_phys(const hb_params* prm, double shift) {
+  Phys p;
+  p.rho = prm->rho;
+  p.mu = prm->mu;
+  p.nu = prm->mu / prm->rho;
+  p.C_I = prm->C_I;
+  p.beta = prm->beta_bf;
+  p.omega = 6.283185307179586476925286766559 / prm->period;
+  p.shift = shift;
+  p.N = 2 * prm->K + 1;
+  p.backflow = prm->beta_bf > 0 ? 1 : 0;
+  return p;
+}
+
+// Make workspace ready for N samples and the boundary data of bc.
+int prepare(hb_mesh* m, const hb_params* prm, const hb_bc* bc, hipStream_t st) {
+  int rc = check_params(prm);
+  if (rc) return rc;
+  if (!bc || !bc->dirichlet) return fail(HB_ERR_ARG, "bc.dirichlet is NULL");
+  Workspace& w = m->ws;
+  const int N = 2 * prm->K + 1;
+  const int64_t n = m->dm.n;
+  const int nout = m->dm.n_out;
+  if (w.N != N) {
+    HB_CHECK(w.Sy.ensure(sizeof(double) * n * hb::NCH * N));
+    HB_CHECK(w.Sv.ensure(sizeof(double) * n * hb::NCH * N));
+    HB_CHECK(w.acc.ensure(sizeof(double) * n * hb::NCH * N));
+    HB_CHECK(w.dg.ensure(sizeof(double) * n * 2 * N));
+    HB_CHECK(w.dinv.ensure(sizeof(double) * n * 2 * N));
+    HB_CHECK(w.tab.ensure(sizeof(double) * hb::TAB_COUNT * N * N));
+    // small: Q, dQ, hs (n_out N each), R (n_out), flag
+    HB_CHECK(w.small.ensure(sizeof(double) * (3 * (size_t)nout * N + nout + 8)));
+    w.N = N;
+    w.bc_valid = false;
+    w.tab_host.clear();
+  }
+  std::vector<double> tab;
+  build_tables(prm->K, 6.283185307179586476925286766559 / prm->period, tab);
+  if (tab != w.tab_host) {
+    w.tab_host = tab;
+    HB_CHECK(hipMemcpyAsync(w.tab.p, w.tab_host.data(), sizeof(double) * tab.size(),
+                            hipMemcpyHostToDevice, st));
+  }
+  // outlet traction samples h_n (from modal coefficients) and resistances
+  std::vector<double> bch((size_t)nout * N + nout, 0.0);
+  if (bc->outlet_h) {
+    const double* Binv = tab.data() + hb::TAB_BINV * (size_t)N * N;
+    for (int k = 0; k < nout; ++k)
+      for (int s = 0; s < N; ++s) {
+        double v = 0.0;
+        for (int mm = 0; mm < N; ++mm) v += Binv[s * N + mm] * bc->outlet_h[(size_t)k * N + mm];
+        bch[(size_t)k * N + s] = v;
+      }
+  }
+  if (bc->outlet_R)
+    for (int k = 0; k < nout; ++k) {
+      if (!std::isfinite(bc->outlet_R[k])) return fail(HB_ERR_ARG, "non-finite outlet_R");
+      bch[(size_t)nout * N + k] = bc->outlet_R[k];
+    }
+  const bool hasR = bc->outlet_R != nullptr;
+  if (!w.bc_valid || hasR != w.bc_has_R || bch != w.bc_host) {
+    w.bc_host = bch;
+    w.bc_has_R = hasR;
+    w.bc_valid = true;
+    double* hs = w.small.as<double>() + 2 * (size_t)nout * N;
+    if (!bch.empty())
+      HB_CHECK(hipMemcpyAsync(hs, w.bc_host.data(), sizeof(double) * bch.size(),
+                              hipMemcpyHostToDevice, st));
+  }
+  return HB_OK;
+}
+
+struct Ptrs {
+  double* Q;
+  double* dQ;
+  const double* hs;
+  const double* R;
+  int* flag;
+};
+
+Ptrs small_ptrs(hb_mesh* m) {
+  const int N = m->ws.N;
+  const int nout = m->dm.n_out;
+  double* b = m->ws.small.as<double>();
+  Ptrs p;
+  p.Q = b;
+  p.dQ = b + (size_t)nout * N;
+  p.hs = b + 2 * (size_t)nout * N;
+  p.R = m->ws.bc_has_R ? b + 3 * (size_t)nout * N : nullptr;
+  p.flag = reinterpret_cast<int*>(b + 3 * (size_t)nout * N + nout);
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hb_last_error(void) { return g_err.c_str(); }
+
+int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets,
+                   int64_t n_faces, const int32_t* faces, const int32_t* face_group,
+                   int32_t n_groups, const int32_t* group_kind, hb_mesh** out) {
+  if (!out) return fail(HB_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_nodes <= 0 || n_tets <= 0 || n_faces < 0 || n_groups <= 0)
+    return fail(HB_ERR_ARG, "sizes must be positive");
+  if (n_nodes > INT32_MAX) return fail(HB_ERR_ARG, "more than 2^31-1 nodes");
+  if (!xyz || !tets || (n_faces > 0 && (!faces || !face_group)) || !group_kind)
+    return fail(HB_ERR_ARG, "NULL mesh array");
+  int n_outlets = 0;
+  for (int g = 0; g < n_groups; ++g) {
+    if (group_kind[g] < HB_WALL || group_kind[g] > HB_OUTLET)
+      return fail(HB_ERR_ARG, "group_kind out of range");
+    n_outlets += group_kind[g] == HB_OUTLET;
+  }
+  if (n_outlets == 0) return fail(HB_ERR_ARG, "no outlet group: pressure undetermined");
+  if (n_outlets > 64) return fail(HB_ERR_ARG, "more than 64 outlet groups");
+  for (int64_t i = 0; i < 3 * n_nodes; ++i)
+    if (!std::isfinite(xyz[i])) return fail(HB_ERR_MESH, "non-finite coordinate");
+
+  std::vector<int32_t> T(tets, tets + 4 * n_tets);
+  for (int64_t i = 0; i < 4 * n_tets; ++i)
+    if (T[i] < 0 || T[i] >= n_nodes) return fail(HB_ERR_MESH, "tetrahedron node index out of range");
+  for (int64_t f = 0; f < n_faces; ++f) {
+    for (int k = 0; k < 3; ++k)
+      if (faces[3 * f + k] < 0 || faces[3 * f + k] >= n_nodes)
+        return fail(HB_ERR_MESH, "face node index out of range");
+    if (face_group[f] < 0 || face_group[f] >= n_groups)
+      return fail(HB_ERR_MESH, "face group out of range");
+  }
+
+  auto P = [&](int32_t a, int k) { return xyz[3 * (int64_t)a + k]; };
+  const int64_t ne = n_tets;
+  std::vector<double> geo((size_t)hb::GEO_COUNT * ne);
+  std::vector<double> vol(ne);
+  int64_t reoriented = 0;
+  double vsum = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t t = 0; t < ne; ++t) {
+      int32_t* v = &T[4 * t];
+      double J[3][3];  // columns x_k - x_0
+      for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) J[i][k] = P(v[k + 1], i) - P(v[0], i);
+      const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                       - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                       + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      if (pass == 0) {
+        if (det < 0) {
+          std::swap(v[2], v[3]);
+          ++reoriented;
+          vol[t] = -det / 6.0;
+        } else {
+          vol[t] = det / 6.0;
+        }
+        vsum += vol[t];
+        continue;
+      }
+      // inverse: row k of J^-1 = gradient of barycentric coordinate k+1
+      double Ji[3][3];
+      Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+      Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+      Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+      Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+      for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) geo[(size_t)(hb::GEO_G1 + 3 * k + i) * ne + t] = Ji[k][i];
+      geo[(size_t)hb::GEO_V * ne + t] = det / 6.0;
+      double xi[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          xi[i][j] = Ji[0][i] * Ji[0][j] + Ji[1][i] * Ji[1][j] + Ji[2][i] * Ji[2][j];
+      geo[(size_t)hb::GEO_XI00 * ne + t] = xi[0][0];
+      geo[(size_t)hb::GEO_XI01 * ne + t] = xi[0][1];
+      geo[(size_t)hb::GEO_XI02 * ne + t] = xi[0][2];
+      geo[(size_t)hb::GEO_XI11 * ne + t] = xi[1][1];
+      geo[(size_t)hb::GEO_XI12 * ne + t] = xi[1][2];
+      geo[(size_t)hb::GEO_XI22 * ne + t] = xi[2][2];
+      double xx = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) xx += xi[i][j] * xi[i][j];
+      geo[(size_t)hb::GEO_XIXI * ne + t] = xx;
+    }
+    if (pass == 0) {
+      const double vmean = vsum / ne;
+      for (int64_t t = 0; t < ne; ++t)
+        if (!(vol[t] >= 1e-14 * vmean)) return fail(HB_ERR_MESH, "degenerate tetrahedron");
+    }
+  }
+
+  // node classes: Dirichlet = nodes of wall and inlet faces
+  std::vector<uint8_t> dmask(n_nodes, 0), wall(n_nodes, 0), inlet(n_nodes, 0);
+  std::vector<int32_t> gid2out(n_groups, -1);
+  {
+    int k = 0;
+    for (int g = 0; g < n_groups; ++g)
+      if (group_kind[g] == HB_OUTLET) gid2out[g] = k++;
+  }
+  std::vector<int64_t> ofaces;
+  for (int64_t f = 0; f < n_faces; ++f) {
+    const int kind = group_kind[face_group[f]];
+    for (int k = 0; k < 3; ++k) {
+      const int32_t a = faces[3 * f + k];
+      if (kind == HB_WALL) wall[a] = 1;
+      if (kind == HB_INLET) inlet[a] = 1;
+      if (kind != HB_OUTLET) dmask[a] = 1;
+    }
+    if (kind == HB_OUTLET) ofaces.push_back(f);
+  }
+  const int64_t nof = (int64_t)ofaces.size();
+
+  // outlet faces: find the owning tetrahedron, orient the normal outwards
+  using Key = std::array<int32_t, 3>;
+  std::vector<std::pair<Key, int64_t>> keys(nof);
+  for (int64_t i = 0; i < nof; ++i) {
+    const int32_t* fv = faces + 3 * ofaces[i];
+    Key k = {fv[0], fv[1], fv[2]};
+    std::sort(k.begin(), k.end());
+    keys[i] = {k, i};
+  }
+  std::sort(keys.begin(), keys.end());
+  std::vector<int32_t> opp(nof, -1);
+  static const int loc[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+  if (nof > 0)
+    for (int64_t t = 0; t < ne; ++t)
+      for (int lf = 0; lf < 4; ++lf) {
+        Key k = {T[4 * t + loc[lf][0]], T[4 * t + loc[lf][1]], T[4 * t + loc[lf][2]]};
+        std::sort(k.begin(), k.end());
+        auto it = std::lower_bound(keys.begin(), keys.end(), std::make_pair(k, (int64_t)-1));
+        for (; it != keys.end() && it->first == k; ++it) opp[it->second] = T[4 * t + lf];
+      }
+  std::vector<int32_t> ofv(3 * nof), oid(nof);
+  std::vector<double> ofn(4 * nof);
+  for (int64_t i = 0; i < nof; ++i) {
+    if (opp[i] < 0) return fail(HB_ERR_MESH, "outlet face is not a face of any tetrahedron");
+    const int32_t* fv = faces + 3 * ofaces[i];
+    double a[3], b[3], c[3], nrm[3];
+    for (int k = 0; k < 3; ++k) {
+      a[k] = P(fv[1], k) - P(fv[0], k);
+      b[k] = P(fv[2], k) - P(fv[0], k);
+      c[k] = P(opp[i], k) - P(fv[0], k);
+    }
+    nrm[0] = a[1] * b[2] - a[2] * b[1];
+    nrm[1] = a[2] * b[0] - a[0] * b[2];
+    nrm[2] = a[0] * b[1] - a[1] * b[0];
+    double sgn = nrm[0] * c[0] + nrm[1] * c[1] + nrm[2] * c[2];
+    const double len = std::sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+    if (!(len > 0)) return fail(HB_ERR_MESH, "degenerate outlet face");
+    const double s = sgn > 0 ? -1.0 / len : 1.0 / len;
+    for (int k = 0; k < 3; ++k) {
+      ofv[k * nof + i] = fv[k];
+      ofn[k * nof + i] = nrm[k] * s;
+    }
+    ofn[3 * nof + i] = 0.5 * len;
+    oid[i] = gid2out[face_group[ofaces[i]]];
+  }
+
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
+    return fail(HB_ERR_DEVICE, "no HIP device");
+  std::unique_ptr<hb_mesh> m(new hb_mesh());
+  (void)hipGetDevice(&m->device);
+  std::vector<int32_t> Tsoa(4 * ne);
+  for (int64_t t = 0; t < ne; ++t)
+    for (int k = 0; k < 4; ++k) Tsoa[k * ne + t] = T[4 * t + k];
+  HB_CHECK(m->tets.ensure(sizeof(int32_t) * 4 * ne));
+  HB_CHECK(m->geo.ensure(sizeof(double) * geo.size()));
+  HB_CHECK(m->dmask.ensure(n_nodes));
+  HB_CHECK(m->of.ensure(sizeof(int32_t) * 3 * nof));
+  HB_CHECK(m->ofn.ensure(sizeof(double) * 4 * nof));
+  HB_CHECK(m->oid.ensure(sizeof(int32_t) * nof));
+  HB_CHECK(hipMemcpy(m->tets.p, Tsoa.data(), sizeof(int32_t) * 4 * ne, hipMemcpyHostToDevice));
+  HB_CHECK(hipMemcpy(m->geo.p, geo.data(), sizeof(double) * geo.size(), hipMemcpyHostToDevice));
+  HB_CHECK(hipMemcpy(m->dmask.p, dmask.data(), n_nodes, hipMemcpyHostToDevice));
+  if (nof) {
+    HB_CHECK(hipMemcpy(m->of.p, ofv.data(), sizeof(int32_t) * 3 * nof, hipMemcpyHostToDevice));
+    HB_CHECK(hipMemcpy(m->ofn.p, ofn.data(), sizeof(double) * 4 * nof, hipMemcpyHostToDevice));
+    HB_CHECK(hipMemcpy(m->oid.p, oid.data(), sizeof(int32_t) * nof, hipMemcpyHostToDevice));
+  }
+  DevMesh& d = m->dm;
+  d.n = n_nodes;
+  d.ne = ne;
+  d.nof = nof;
+  d.n_out = n_outlets;
+  d.tets = m->tets.as<int32_t>();
+  d.geo = m->geo.as<double>();
+  d.dmask = m->dmask.as<uint8_t>();
+  d.of = m->of.as<int32_t>();
+  d.ofn = m->ofn.as<double>();
+  d.oid = m->oid.as<int32_t>();
+  for (int64_t a = 0; a < n_nodes; ++a) {
+    m->n_dirichlet += dmask[a];
+    m->n_inlet += inlet[a];
+    if (inlet[a] && !wall[a]) m->inlet_nodes.push_back((int32_t)a);
+  }
+  m->n_reoriented = reoriented;
+  m->mean_vol = vsum / ne;
+  *out = m.release();
+  return HB_OK;
+}
+
+void hb_mesh_destroy(hb_mesh* mesh) { delete mesh; }
+
+int hb_mesh_info(const hb_mesh* m, int64_t* info) {
+  if (!m || !info) return fail(HB_ERR_ARG, "NULL argument");
+  info[0] = m->dm.n;
+  info[1] = m->dm.ne;
+  info[2] = m->n_dirichlet;
+  info[3] = m->dm.nof;
+  info[4] = m->dm.n_out;
+  info[5] = m->n_reoriented;
+  info[6] = m->n_inlet;
+  info[7] = (int64_t)m->bytes_held();
+  return HB_OK;
+}
+
+int hb_residual(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+                double* R, void* stream) {
+  if (!mesh || !Y || !R) return fail(HB_ERR_ARG, "NULL argument");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = prepare(m, prm, bc, st);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  const int N = w.N;
+  const Phys p = make_phys(prm, 0.0);
+  Ptrs s = small_ptrs(m);
+  const double* tab = w.tab.as<double>();
+  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(),
+                                w.acc.as<double>(), s.Q, m->dm.n_out * N, st));
+  if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, w.Sy.as<double>(), s.Q, st));
+  HB_CHECK(hb::elem_residual(m->dm, p, w.Sy.as<double>(), w.acc.as<double>(), st));
+  HB_CHECK(hb::face_residual(m->dm, p, w.Sy.as<double>(), s.hs, s.R, s.Q, w.acc.as<double>(), st));
+  HB_CHECK(hb::samples_to_modal(m->dm, N, w.acc.as<double>(), 1, 1, hb::NCH, tab, R, st));
+  return HB_OK;
+}
+
+int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+           const void* V, void* JV, int32_t flags, void* stream) {
+  if (!mesh || !Y || !V || !JV) return fail(HB_ERR_ARG, "NULL argument");
+  if (flags & ~3) return fail(HB_ERR_ARG, "unknown flags");
+  if (flags & HB_F32) return fail(HB_ERR_ARG, "HB_F32 vectors are not supported by hb_jvp");
+  const int kind = flags & 1;
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = prepare(m, prm, bc, st);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  const int N = w.N;
+  const Phys p = make_phys(prm, 0.0);
+  Ptrs s = small_ptrs(m);
+  const double* tab = w.tab.as<double>();
+  double* Sy = w.Sy.as<double>();
+  double* Sv = w.Sv.as<double>();
+  double* acc = w.acc.as<double>();
+  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, Sy, nullptr, nullptr, 0, st));
+  HB_CHECK(hb::modal_to_samples(m->dm, N, (const double*)V, bc->dirichlet, 1, tab, Sv, acc, s.dQ,
+                                m->dm.n_out * N, st));
+  if (kind == HB_JV_EXACT) {
+    if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
+    HB_CHECK(hb::elem_jvp_exact(m->dm, p, Sy, Sv, acc, st));
+    HB_CHECK(hb::face_jvp(m->dm, p, Sy, Sv, s.R, s.dQ, acc, st));
+    HB_CHECK(hb::samples_to_modal(m->dm, N, acc, 1, 1, hb::NCH, tab, (double*)JV, st));
+  } else {
+    HB_CHECK(hb::elem_jvp_paper(m->dm, p, Sy, Sv, acc, st));
+    HB_CHECK(hb::samples_to_modal(m->dm, N, acc, 0, 1, hb::NCH, tab, (double*)JV, st));
+  }
+  return HB_OK;
+}
+
+int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+              double shift, double* D, void* stream) {
+  if (!mesh || !Y || !D) return fail(HB_ERR_ARG, "NULL argument");
+  if (!std::isfinite(shift) || shift < 0) return fail(HB_ERR_ARG, "shift must be finite, >= 0");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = prepare(m, prm, bc, st);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  const int N = w.N;
+  const Phys p = make_phys(prm, shift);
+  const double* tab = w.tab.as<double>();
+  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(), nullptr,
+                                nullptr, 0, st));
+  HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * 2 * N, st));
+  HB_CHECK(hb::elem_jacobi(m->dm, p, w.Sy.as<double>(), w.dg.as<double>(), st));
+  HB_CHECK(hb::jacobi_out(m->dm, N, w.dg.as<double>(), D, nullptr, st));
+  return HB_OK;
+}
+
+// ------------------------------------------------------------ the solver
+
+namespace {
+
+struct Solver {
+  hb_mesh* m;
+  const hb_params* prm;
+  hipStream_t st;
+  int N;
+  int64_t L;
+  int restart;
+  int nblk;
+  int jv_kind;
+  DevBuf basis, xvec, rvec, tmp, partial, hdev;
+  std::vector<double> hhost;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double jv_ms = 0.0;
+  int n_jv = 0;
+
+  ~Solver() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+
+  double* Q(int j) { return basis.as<double>() + (size_t)j * L; }
+
+  int residual(double* r, double& nrm) {
+    Workspace& w = m->ws;
+    Ptrs s = small_ptrs(m);
+    const double* tab = w.tab.as<double>();
+    const Phys p = make_phys(prm, 0.0);
+    double* Sy = w.Sy.as<double>();
+    HB_CHECK(hb::prepare_direction(m->dm, N, Sy, hb::NCH, nullptr, 0, tab, Sy, w.acc.as<double>(),
+                                   s.Q, m->dm.n_out * N, st));
+    if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sy, s.Q, st));
+    HB_CHECK(hb::elem_residual(m->dm, p, Sy, w.acc.as<double>(), st));
+    HB_CHECK(hb::face_residual(m->dm, p, Sy, s.hs, s.R, s.Q, w.acc.as<double>(), st));
+    HB_CHECK(hb::finish_rows(m->dm, N, w.acc.as<double>(), 1, tab, nullptr, r, st));
+    return norm(r, nrm);
+  }
+
+  int norm(const double* x, double& out) {
+    HB_CHECK(hb::vec_dots(x, L, 1, x, L, partial.as<double>(), nblk, hdev.as<double>(), st));
+    double v = 0.0;
+    HB_CHECK(hipMemcpyAsync(&v, hdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HB_CHECK(hipStreamSynchronize(st));
+    out = std::sqrt(v);
+    return HB_OK;
+  }
+
+  // w = J M^-1 q (+ shift mass), Dirichlet momentum rows = q.
+  int apply(const double* q, double* wout, double shift) {
+    Workspace& w = m->ws;
+    Ptrs s = small_ptrs(m);
+    const double* tab = w.tab.as<double>();
+    const Phys p = make_phys(prm, shift);
+    double* Sv = w.Sv.as<double>();
+    double* acc = w.acc.as<double>();
+    HB_CHECK(hipEventRecord(ev0, st));
+    HB_CHECK(hb::prepare_direction(m->dm, N, q, 4, w.dinv.as<double>(), 1, tab, Sv, acc, s.dQ,
+                                   m->dm.n_out * N, st));
+    if (jv_kind == HB_JV_EXACT) {
+      if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
+      HB_CHECK(hb::elem_jvp_exact(m->dm, p, w.Sy.as<double>(), Sv, acc, st));
+      HB_CHECK(hb::face_jvp(m->dm, p, w.Sy.as<double>(), Sv, s.R, s.dQ, acc, st));
+      HB_CHECK(hb::finish_rows(m->dm, N, acc, 1, tab, q, wout, st));
+    } else {
+      HB_CHECK(hb::elem_jvp_paper(m->dm, p, w.Sy.as<double>(), Sv, acc, st));
+      HB_CHECK(hb::finish_rows(m->dm, N, acc, 0, tab, q, wout, st));
+    }
+    HB_CHECK(hipEventRecord(ev1, st));
+    HB_CHECK(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    HB_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+    jv_ms += ms;
+    ++n_jv;
+    return HB_OK;
+  }
+
+  // Right-preconditioned restarted GMRES on (J M^-1) x = -r; CGS2.
+  int gmres(const double* r, double shift, double eta, int max_it, int& iters) {
+    double* x = xvec.as<double>();
+    double* rl = rvec.as<double>();
+    HB_CHECK(hb::vec_zero(x, L, st));
+    HB_CHECK(hb::vec_copy_scaled(rl, r, L, -1.0, st));
+    double beta;
+    int rc = norm(rl, beta);
+    if (rc) return rc;
+    iters = 0;
+    if (beta == 0.0) return HB_OK;
+    const double target = eta * beta;
+    const int mr = restart;
+    std::vector<double> Hm((size_t)(mr + 1) * mr), cs(mr), sn(mr), g(mr + 1), yv(mr);
+    hhost.assign(2 * (mr + 1) + 1, 0.0);
+    double bc = beta;
+    while (true) {
+      HB_CHECK(hb::vec_copy_scaled(Q(0), rl, L, 1.0 / bc, st));
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = bc;
+      int jend = 0;
+      bool done = false;
+      for (int j = 0; j < mr; ++j) {
+        double* wj = Q(j + 1);
+        rc = apply(Q(j), wj, shift);
+        if (rc) return rc;
+        double* h1 = hdev.as<double>();
+        double* h2 = h1 + (mr + 1);
+        double* h3 = h2 + (mr + 1);
+        HB_CHECK(hb::vec_dots(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h1, st));
+        HB_CHECK(hb::vec_axpy_multi(wj, Q(0), L, j + 1, h1, -1.0, L, st));
+        HB_CHECK(hb::vec_dots(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h2, st));
+        HB_CHECK(hb::vec_axpy_multi(wj, Q(0), L, j + 1, h2, -1.0, L, st));
+        HB_CHECK(hb::vec_dots(wj, L, 1, wj, L, partial.as<double>(), nblk, h3, st));
+        HB_CHECK(hipMemcpyAsync(hhost.data(), h1, sizeof(double) * (2 * (mr + 1) + 1),
+                                hipMemcpyDeviceToHost, st));
+        HB_CHECK(hipStreamSynchronize(st));
+        double* col = &Hm[(size_t)j * (mr + 1)];
+        for (int k = 0; k <= j; ++k) col[k] = hhost[k] + hhost[(mr + 1) + k];
+        const double hn = std::sqrt(std::max(hhost[2 * (mr + 1)], 0.0));
+        col[j + 1] = hn;
+        if (!std::isfinite(hn)) return fail(HB_ERR_NAN, "non-finite Krylov vector");
+        if (hn > 0) HB_CHECK(hb::vec_scale(wj, L, nullptr, 1.0 / hn, st));
+        for (int k = 0; k < j; ++k) {
+          const double a = col[k], b = col[k + 1];
+          col[k] = cs[k] * a + sn[k] * b;
+          col[k + 1] = -sn[k] * a + cs[k] * b;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        cs[j] = den > 0 ? col[j] / den : 1.0;
+        sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++iters;
+        jend = j + 1;
+        if (std::fabs(g[j + 1]) <= target || iters >= max_it || hn == 0.0) {
+          done = true;
+          break;
+        }
+      }
+      for (int i = jend - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int k = i + 1; k < jend; ++k) v -= Hm[(size_t)k * (mr + 1) + i] * yv[k];
+        const double d = Hm[(size_t)i * (mr + 1) + i];
+        yv[i] = d != 0.0 ? v / d : 0.0;
+      }
+      double* ydev = hdev.as<double>() + 2 * (mr + 1) + 1;
+      HB_CHECK(hipMemcpyAsync(ydev, yv.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
+      HB_CHECK(hb::vec_axpy_multi(x, Q(0), L, jend, ydev, 1.0, L, st));
+      HB_CHECK(hipStreamSynchronize(st));
+      if (done && (std::fabs(g[jend]) <= target || iters >= max_it)) break;
+      // restart: rl = -r - (J M^-1) x
+      rc = apply(x, tmp.as<double>(), shift);
+      if (rc) return rc;
+      HB_CHECK(hb::vec_copy_scaled(rl, r, L, -1.0, st));
+      double one = 1.0;
+      HB_CHECK(hipMemcpyAsync(ydev, &one, sizeof(double), hipMemcpyHostToDevice, st));
+      HB_CHECK(hb::vec_axpy_multi(rl, tmp.as<double>(), L, 1, ydev, -1.0, L, st));
+      rc = norm(rl, bc);
+      if (rc) return rc;
+      if (bc <= target || iters >= max_it) break;
+    }
+    return HB_OK;
+  }
+};
+
+}  // namespace
+
+int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
+                    const hb_solve_opts* opts, hb_solve_report* report, void* stream) {
+  if (!mesh || !Y || !opts || !report) return fail(HB_ERR_ARG, "NULL argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  std::memset(report, 0, sizeof(*report));
+  report->status = HB_ERR_NOCONV;
+  if (opts->precision != HB_F64) return fail(HB_ERR_ARG, "only precision = HB_F64 is available");
+  if (opts->restart < 1 || opts->restart > 512) return fail(HB_ERR_ARG, "restart must be 1..512");
+  if (opts->max_newton < 0 || opts->max_gmres < 1) return fail(HB_ERR_ARG, "bad iteration limits");
+  if (!(opts->rtol > 0) || !(opts->gmres_eta > 0) || !(opts->cfl > 0) || !(opts->c1 >= 0))
+    return fail(HB_ERR_ARG, "rtol, gmres_eta, cfl must be positive");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = prepare(m, prm, bc, st);
+  if (rc) return rc;
+  Solver S;
+  S.m = m;
+  S.prm = prm;
+  S.st = st;
+  S.N = m->ws.N;
+  S.L = m->dm.n * 4 * S.N;
+  S.restart = opts->restart;
+  S.nblk = 1024;
+  S.jv_kind = opts->jv_kind == HB_JV_PAPER ? HB_JV_PAPER : HB_JV_EXACT;
+  const int N = S.N;
+  const int64_t L = S.L;
+  HB_CHECK(S.basis.ensure(sizeof(double) * (size_t)(S.restart + 1) * L));
+  HB_CHECK(S.xvec.ensure(sizeof(double) * L));
+  HB_CHECK(S.rvec.ensure(sizeof(double) * L));
+  HB_CHECK(S.tmp.ensure(sizeof(double) * L));
+  HB_CHECK(S.partial.ensure(sizeof(double) * (size_t)(S.restart + 2) * S.nblk));
+  HB_CHECK(S.hdev.ensure(sizeof(double) * (4 * (size_t)(S.restart + 1) + 8)));
+  HB_CHECK(hipEventCreate(&S.ev0));
+  HB_CHECK(hipEventCreate(&S.ev1));
+  Workspace& w = m->ws;
+  const double* tab = w.tab.as<double>();
+  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(), nullptr,
+                                nullptr, 0, st));
+
+  // initial pseudo step: dt = cfl h_c / u_c (Section 2.3)
+  const double hc = std::cbrt(6.0 * std::sqrt(2.0) * m->mean_vol);
+  double uc = 0.0;
+  if (!m->inlet_nodes.empty()) {
+    std::vector<double> dh((size_t)3 * N * m->dm.n);
+    HB_CHECK(hipMemcpyAsync(dh.data(), bc->dirichlet, sizeof(double) * dh.size(),
+                            hipMemcpyDeviceToHost, st));
+    HB_CHECK(hipStreamSynchronize(st));
+    const double* Binv = w.tab_host.data() + hb::TAB_BINV * (size_t)N * N;
+    for (int s = 0; s < N; ++s) {
+      double sum = 0.0;
+      for (int32_t a : m->inlet_nodes) {
+        double g2 = 0.0;
+        for (int i = 0; i < 3; ++i) {
+          double v = 0.0;
+          for (int mm = 0; mm < N; ++mm)
+            v += Binv[s * N + mm] * dh[((size_t)i * N + mm) * m->dm.n + a];
+          g2 += v * v;
+        }
+        sum += std::sqrt(g2);
+      }
+      uc = std::max(uc, sum / (double)m->inlet_nodes.size());
+    }
+  }
+  const double dt0 = uc > 0 ? opts->cfl * hc / uc : opts->cfl * hc;
+  double dt = dt0;
+
+  DevBuf rbuf;
+  HB_CHECK(rbuf.ensure(sizeof(double) * L));
+  double* r = rbuf.as<double>();
+  double rn = 0.0;
+  rc = S.residual(r, rn);
+  if (rc) return rc;
+  report->r0 = rn;
+  if (!std::isfinite(rn)) return fail(HB_ERR_NAN, "non-finite initial residual");
+  const double ref = opts->r_ref > 0 ? opts->r_ref : rn;
+  report->r_ref = ref;
+  int status = HB_ERR_NOCONV;
+  int it = 0;
+  for (;; ++it) {
+    if (rn <= opts->rtol * ref) {
+      status = HB_OK;
+      break;
+    }
+    if (it >= opts->max_newton) break;
+    const double shift = opts->c1 * prm->rho / dt;
+    const Phys pj = make_phys(prm, shift);
+    HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * 2 * N, st));
+    HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), st));
+    HB_CHECK(hb::jacobi_out(m->dm, N, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
+    int gi = 0;
+    rc = S.gmres(r, shift, opts->gmres_eta, opts->max_gmres, gi);
+    if (rc) return rc;
+    report->gmres_iters += gi;
+    HB_CHECK(hb::vec_mul_dinv_add(w.Sy.as<double>(), S.xvec.as<double>(), w.dinv.as<double>(),
+                                  m->dm.dmask, m->dm.n, N, hb::NCH, 1.0, st));
+    double rn_new = 0.0;
+    rc = S.residual(r, rn_new);
+    if (rc) return rc;
+    if (!std::isfinite(rn_new)) {
+      report->newton_iters = it + 1;
+      return fail(HB_ERR_NAN, "non-finite residual");
+    }
+    dt = std::min(dt * rn / std::max(rn_new, 1e-300), 1e6 * dt0);
+    rn = rn_new;
+    if (opts->verbose)
+      std::fprintf(stderr, "hb newton %d: |r| = %.3e  gmres %d  dt %.3e\n", it + 1, rn, gi, dt);
+  }
+  report->newton_iters = it;
+  report->r_final = rn;
+  HB_CHECK(hb::samples_to_modal(m->dm, N, w.Sy.as<double>(), 0, 0, hb::NCH, tab, Y, st));
+  HB_CHECK(hipStreamSynchronize(st));
+  report->status = status;
+  report->jv_ms = S.jv_ms;
+  report->n_jv = S.n_jv;
+  report->wall_s =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (status != HB_OK) return fail(status, "Newton iteration limit reached");
+  return HB_OK;
+}
+
+}  // extern "C"

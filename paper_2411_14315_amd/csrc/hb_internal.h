@@ -1,0 +1,97 @@
+// Internal declarations shared by the kernel and host translation units of
+// the HB library.  Not part of the public interface (see include/hb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hb {
+
+// Library-owned device view of a mesh (structure of arrays).
+struct DevMesh {
+  int64_t n = 0;      // nodes
+  int64_t ne = 0;     // tetrahedra
+  int64_t nof = 0;    // outlet triangles
+  int32_t n_out = 0;  // outlet groups
+  const int32_t* tets = nullptr;  // [4][ne]
+  const double* geo = nullptr;    // [GEO_COUNT][ne]
+  const uint8_t* dmask = nullptr; // [n] 1 on Dirichlet nodes
+  const int32_t* of = nullptr;    // [3][nof] outlet triangle nodes
+  const double* ofn = nullptr;    // [4][nof] unit outward normal, area
+  const int32_t* oid = nullptr;   // [nof] outlet index
+};
+
+// Per-tetrahedron geometry rows: gradients of N_1..N_3 (N_0 = -sum), volume,
+// the upper triangle of xi = J^-T J^-1 and xi:xi.
+enum {
+  GEO_G1 = 0, GEO_G2 = 3, GEO_G3 = 6, GEO_V = 9,
+  GEO_XI00 = 10, GEO_XI01 = 11, GEO_XI02 = 12, GEO_XI11 = 13, GEO_XI12 = 14, GEO_XI22 = 15,
+  GEO_XIXI = 16, GEO_COUNT = 17
+};
+
+struct Phys {
+  double rho, mu, nu, C_I, beta, omega;
+  double shift;      // pseudo-time mass coefficient on velocity rows (0 = none)
+  int32_t N;
+  int32_t backflow;  // 1 = backflow term on outlets
+};
+
+// Time-axis tables, each N x N doubles, stored consecutively.
+enum {
+  TAB_BINV = 0,  // [s][m] samples = Binv . modal
+  TAB_BDER = 1,  // [s][m] d/dt samples = Bder . modal
+  TAB_FWD = 2,   // [m][s] modal = Fwd . samples
+  TAB_FWDD = 3,  // [m][s] modal(H x) = FwdD . samples(x)
+  TAB_H = 4,     // [s][k] H in samples
+  TAB_COUNT = 5
+};
+
+// Samples buffers are node-major: X[a][c][s] with c a channel.  The state
+// and direction buffers carry 7 channels (u1 u2 u3 p Hu1 Hu2 Hu3); the
+// element accumulator carries 7 channels (r^m_1..3, r^c, z_1..3); Krylov
+// vectors carry 4 channels.
+constexpr int NCH = 7;
+
+hipError_t modal_to_samples(const DevMesh& m, int N, const double* Y, const double* dir,
+                            int zero_dirichlet, const double* tab, double* S, double* acc_zero,
+                            double* q_zero, int nq, hipStream_t st);
+hipError_t samples_to_modal(const DevMesh& m, int N, const double* acc, int use_z,
+                            int zero_dir_rows, int in_ch, const double* tab, double* R,
+                            hipStream_t st);
+hipError_t outlet_flux(const DevMesh& m, int N, const double* S, double* Q, hipStream_t st);
+hipError_t elem_residual(const DevMesh& m, const Phys& p, const double* S, double* acc,
+                         hipStream_t st);
+hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
+                          double* acc, hipStream_t st);
+hipError_t elem_jvp_paper(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
+                          double* acc, hipStream_t st);
+hipError_t elem_jacobi(const DevMesh& m, const Phys& p, const double* Sy, double* dg,
+                       hipStream_t st);
+hipError_t face_residual(const DevMesh& m, const Phys& p, const double* S, const double* hs,
+                         const double* Rk, const double* Q, double* acc, hipStream_t st);
+hipError_t face_jvp(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
+                    const double* Rk, const double* dQ, double* acc, hipStream_t st);
+hipError_t jacobi_out(const DevMesh& m, int N, const double* dg, double* D, double* dinv,
+                      hipStream_t st);
+// sample-space nodal passes (Krylov path)
+hipError_t prepare_direction(const DevMesh& m, int N, const double* q, int in_ch,
+                             const double* dinv, int zero_dirichlet, const double* tab,
+                             double* Sv, double* acc_zero, double* q_zero, int nq,
+                             hipStream_t st);
+hipError_t finish_rows(const DevMesh& m, int N, const double* acc, int use_z, const double* tab,
+                       const double* id_rows, double* out, hipStream_t st);
+// vectors
+hipError_t vec_dots(const double* Q, int64_t ld, int k, const double* w, int64_t L,
+                    double* partial, int nblk, double* out, hipStream_t st);
+hipError_t vec_axpy_multi(double* w, const double* Q, int64_t ld, int k, const double* h,
+                          double sign, int64_t L, hipStream_t st);
+hipError_t vec_scale(double* x, int64_t L, const double* inv_scalar, double s_host,
+                     hipStream_t st);
+hipError_t vec_copy_scaled(double* dst, const double* src, int64_t L, double s, hipStream_t st);
+hipError_t vec_zero(double* x, int64_t L, hipStream_t st);
+hipError_t vec_mul_dinv_add(double* y, const double* u, const double* dinv, const uint8_t* dmask,
+                            int64_t n, int N, int nch_y, double s, hipStream_t st);
+hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st);
+
+}  // namespace hb

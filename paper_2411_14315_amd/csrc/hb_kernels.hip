@@ -1,0 +1,1089 @@
+// HIP kernels of the harmonic-balance GLS Navier-Stokes operator for gfx950.
+//
+// The operator (Jia & Esmaily, arXiv 2411.14315, Section 2.3, eq. Rmc) is
+// pointwise in time except for the time-coupling matrix H (Section 2.1,
+// eq. NS-harm).  The hot path is split accordingly:
+//
+//   node tiles   modal <-> time-sample transforms and H products, one small
+//                dense N x N contraction per node and field, staged through
+//                LDS so that every global access is a contiguous run;
+//   elements     one lane per (tetrahedron, sample): gather the four nodes'
+//                samples, evaluate the Galerkin and GLS terms at the 4-point
+//                quadrature, scatter the 4 x 7 node rows with hardware FP64
+//                atomics; workgroups are mapped so that each XCD (own L2)
+//                walks a contiguous range of elements;
+//   faces        one lane per (outlet triangle, sample): traction,
+//                resistance and backflow terms.
+//
+// Layouts: modal arrays [f][m][node]; sample buffers node-major
+// [node][channel][sample], so the N lanes of one element read N contiguous
+// doubles per node and channel.
+#include "hb_internal.h"
+
+namespace hb {
+
+namespace {
+
+constexpr int BLK = 256;
+constexpr int TN = 32;  // nodes per transform tile
+// 4-point degree-2 tetrahedron rule: barycentric (a, b, b, b) and permutations.
+constexpr double QA = 0.58541019662496845446137605030969;
+constexpr double QB = 0.13819660112501051517954131656344;
+constexpr double TRI_A = 2.0 / 3.0, TRI_B = 1.0 / 6.0;
+
+// Map the hardware workgroup id to a logical one so that the XCD that
+// receives workgroups b, b+8, b+16, ... processes one contiguous range.
+__device__ __forceinline__ int64_t xcd_block(int64_t nlogical) {
+  const int64_t g = gridDim.x;
+  const int64_t per = g >> 3;
+  const int64_t b = blockIdx.x;
+  const int64_t lb = (b & 7) * per + (b >> 3);
+  return lb < nlogical ? lb : -1;
+}
+
+inline unsigned xcd_grid(int64_t nlogical) {
+  int64_t g = (nlogical + 7) & ~int64_t(7);
+  return (unsigned)g;
+}
+
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+struct Geo {
+  double g[4][3];
+  double V, x00, x01, x02, x11, x12, x22, xixi;
+};
+
+__device__ __forceinline__ void load_geo(const double* __restrict__ geo, int64_t ne, int64_t t,
+                                         Geo& G) {
+#pragma unroll
+  for (int A = 1; A < 4; ++A)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) G.g[A][i] = geo[(GEO_G1 + 3 * (A - 1) + i) * ne + t];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) G.g[0][i] = -(G.g[1][i] + G.g[2][i] + G.g[3][i]);
+  G.V = geo[GEO_V * ne + t];
+  G.x00 = geo[GEO_XI00 * ne + t];
+  G.x01 = geo[GEO_XI01 * ne + t];
+  G.x02 = geo[GEO_XI02 * ne + t];
+  G.x11 = geo[GEO_XI11 * ne + t];
+  G.x12 = geo[GEO_XI12 * ne + t];
+  G.x22 = geo[GEO_XI22 * ne + t];
+  G.xixi = geo[GEO_XIXI * ne + t];
+}
+
+__device__ __forceinline__ void xi_mul(const Geo& G, const double u[3], double o[3]) {
+  o[0] = G.x00 * u[0] + G.x01 * u[1] + G.x02 * u[2];
+  o[1] = G.x01 * u[0] + G.x11 * u[1] + G.x12 * u[2];
+  o[2] = G.x02 * u[0] + G.x12 * u[1] + G.x22 * u[2];
+}
+
+// ------------------------------------------------------------ node tiles
+
+// Modal Y[f][m][a] -> samples S[a][c][s]: c = 0..3 values, 4..6 time
+// derivative of the velocity (H u).  Dirichlet velocity entries are replaced
+// by the boundary data (zero_dirichlet = 0) or by zero (= 1).  Optionally
+// clears the element accumulator of the tile and a short vector.
+__global__ void __launch_bounds__(BLK)
+k_modal_to_samples(int64_t n, int N, const double* __restrict__ Y, const double* __restrict__ dir,
+                   const uint8_t* __restrict__ dmask, int zero_dirichlet,
+                   const double* __restrict__ tab, double* __restrict__ S,
+                   double* __restrict__ acc, double* __restrict__ qz, int nq) {
+  extern __shared__ double sm[];
+  double* sY = sm;              // [4][N][TN]
+  double* sB = sY + 4 * N * TN; // Binv [s][m]
+  double* sD = sB + N * N;      // Bder [s][m]
+  const int64_t a0 = (int64_t)blockIdx.x * TN;
+  const int tn = (int)min<int64_t>(TN, n - a0);
+  const int NN = N * N;
+  for (int i = threadIdx.x; i < NN; i += BLK) {
+    sB[i] = tab[TAB_BINV * NN + i];
+    sD[i] = tab[TAB_BDER * NN + i];
+  }
+  for (int i = threadIdx.x; i < 4 * N * TN; i += BLK) {
+    const int al = i % TN;
+    const int fm = i / TN;
+    double v = 0.0;
+    if (al < tn) {
+      const int64_t a = a0 + al;
+      v = Y[(int64_t)fm * n + a];
+      if (fm < 3 * N && dmask[a]) v = zero_dirichlet ? 0.0 : dir[(int64_t)fm * n + a];
+    }
+    sY[i] = v;
+  }
+  if (acc) {
+    double* ap = acc + a0 * NCH * N;
+    for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) ap[i] = 0.0;
+  }
+  if (qz && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nq; i += BLK) qz[i] = 0.0;
+  __syncthreads();
+  for (int it = threadIdx.x; it < tn * N; it += BLK) {
+    const int al = it / N;
+    const int s = it - al * N;
+    double o[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int m = 0; m < N; ++m) {
+      const double b = sB[s * N + m];
+      const double d = sD[s * N + m];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) o[f] += b * sY[(f * N + m) * TN + al];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) o[4 + f] += d * sY[(f * N + m) * TN + al];
+    }
+    double* out = S + (a0 + al) * NCH * N + s;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) out[c * N] = o[c];
+  }
+}
+
+// Samples acc[a][c][s] -> modal R[f][m][a].  Momentum rows receive -H z,
+// i.e. -FwdD applied to the z channels (use_z), and are zeroed at Dirichlet
+// nodes when zero_dir_rows.
+__global__ void __launch_bounds__(BLK)
+k_samples_to_modal(int64_t n, int N, const double* __restrict__ acc, int use_z, int zero_dir_rows,
+                   int in_ch, const uint8_t* __restrict__ dmask, const double* __restrict__ tab,
+                   double* __restrict__ R) {
+  extern __shared__ double sm[];
+  const int CN = in_ch * N;
+  double* sA = sm;              // [TN][in_ch][N]
+  double* sF = sA + TN * CN;    // Fwd [m][s]
+  double* sG = sF + N * N;      // FwdD [m][s]
+  const int64_t a0 = (int64_t)blockIdx.x * TN;
+  const int tn = (int)min<int64_t>(TN, n - a0);
+  const int NN = N * N;
+  for (int i = threadIdx.x; i < NN; i += BLK) {
+    sF[i] = tab[TAB_FWD * NN + i];
+    sG[i] = tab[TAB_FWDD * NN + i];
+  }
+  const double* ap = acc + a0 * CN;
+  for (int i = threadIdx.x; i < tn * CN; i += BLK) sA[i] = ap[i];
+  __syncthreads();
+  for (int it = threadIdx.x; it < 4 * N * tn; it += BLK) {
+    const int al = it % tn;
+    const int fm = it / tn;
+    const int f = fm / N;
+    const int m = fm - f * N;
+    const double* row = sA + al * CN;
+    double v = 0.0;
+    for (int s = 0; s < N; ++s) v += sF[m * N + s] * row[f * N + s];
+    if (f < 3) {
+      if (use_z)
+        for (int s = 0; s < N; ++s) v -= sG[m * N + s] * row[(4 + f) * N + s];
+      if (zero_dir_rows && dmask[a0 + al]) v = 0.0;
+    }
+    R[(int64_t)fm * n + a0 + al] = v;
+  }
+}
+
+// Sample-space direction: v = dinv * q (velocity entries of Dirichlet nodes
+// zeroed if zero_dirichlet), then Sv[a][0..3] = v and Sv[a][4..6] = H v.
+// q may alias Sv when in_ch == NCH (state update in place).
+__global__ void __launch_bounds__(BLK)
+k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict__ dinv,
+          int zero_dirichlet, const uint8_t* __restrict__ dmask, const double* __restrict__ tab,
+          double* Sv, double* __restrict__ acc, double* __restrict__ qz, int nq) {
+  extern __shared__ double sm[];
+  double* sV = sm;              // [TN][4][N]
+  double* sH = sV + TN * 4 * N; // H [s][k]
+  const int64_t a0 = (int64_t)blockIdx.x * TN;
+  const int tn = (int)min<int64_t>(TN, n - a0);
+  const int NN = N * N;
+  for (int i = threadIdx.x; i < NN; i += BLK) sH[i] = tab[TAB_H * NN + i];
+  for (int i = threadIdx.x; i < tn * 4 * N; i += BLK) {
+    const int al = i / (4 * N);
+    const int r = i - al * 4 * N;
+    const int c = r / N;
+    const int s = r - c * N;
+    const int64_t a = a0 + al;
+    double v = q[(a * in_ch + c) * N + s];
+    if (dinv) v *= dinv[(a * 2 + (c < 3 ? 0 : 1)) * N + s];
+    if (zero_dirichlet && c < 3 && dmask[a]) v = 0.0;
+    sV[i] = v;
+  }
+  if (acc) {
+    double* ap = acc + a0 * NCH * N;
+    for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) ap[i] = 0.0;
+  }
+  if (qz && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nq; i += BLK) qz[i] = 0.0;
+  __syncthreads();
+  for (int it = threadIdx.x; it < tn * N; it += BLK) {
+    const int al = it / N;
+    const int s = it - al * N;
+    const double* v = sV + al * 4 * N;
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double hk = sH[s * N + k];
+      h0 += hk * v[k];
+      h1 += hk * v[N + k];
+      h2 += hk * v[2 * N + k];
+    }
+    double* out = Sv + (a0 + al) * NCH * N + s;
+    out[0] = v[s];
+    out[N] = v[N + s];
+    out[2 * N] = v[2 * N + s];
+    out[3 * N] = v[3 * N + s];
+    out[4 * N] = h0;
+    out[5 * N] = h1;
+    out[6 * N] = h2;
+  }
+}
+
+// Sample-space rows: out[a][i][s] = acc r^m_i - (H z_i) (use_z), out[a][3] =
+// r^c; Dirichlet momentum rows take id_rows (identity) or zero.
+__global__ void __launch_bounds__(BLK)
+k_finish(int64_t n, int N, const double* __restrict__ acc, int use_z,
+         const uint8_t* __restrict__ dmask, const double* __restrict__ tab,
+         const double* __restrict__ id_rows, double* __restrict__ out) {
+  extern __shared__ double sm[];
+  double* sA = sm;                 // [TN][7][N]
+  double* sH = sA + TN * NCH * N;
+  const int64_t a0 = (int64_t)blockIdx.x * TN;
+  const int tn = (int)min<int64_t>(TN, n - a0);
+  const int NN = N * N;
+  for (int i = threadIdx.x; i < NN; i += BLK) sH[i] = tab[TAB_H * NN + i];
+  const double* ap = acc + a0 * NCH * N;
+  for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) sA[i] = ap[i];
+  __syncthreads();
+  for (int it = threadIdx.x; it < tn * 4 * N; it += BLK) {
+    const int al = it / (4 * N);
+    const int r = it - al * 4 * N;
+    const int c = r / N;
+    const int s = r - c * N;
+    const int64_t a = a0 + al;
+    const double* row = sA + al * NCH * N;
+    double v = row[c * N + s];
+    if (c < 3) {
+      if (use_z) {
+        const double* z = row + (4 + c) * N;
+        for (int k = 0; k < N; ++k) v -= sH[s * N + k] * z[k];
+      }
+      if (dmask[a]) v = id_rows ? id_rows[(a * 4 + c) * N + s] : 0.0;
+    }
+    out[(a * 4 + c) * N + s] = v;
+  }
+}
+
+// ------------------------------------------------------------- elements
+
+// Scatter of one element-sample's 4 x 7 rows.
+__device__ __forceinline__ void scatter_rows(double* __restrict__ acc, const int64_t base[4],
+                                             int N, const double rm[4][3], const double rc[4],
+                                             const double z[4][3], bool with_z) {
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    double* p = acc + base[A];
+    atomic_add(p, rm[A][0]);
+    atomic_add(p + N, rm[A][1]);
+    atomic_add(p + 2 * N, rm[A][2]);
+    atomic_add(p + 3 * N, rc[A]);
+    if (with_z) {
+      atomic_add(p + 4 * N, z[A][0]);
+      atomic_add(p + 5 * N, z[A][1]);
+      atomic_add(p + 6 * N, z[A][2]);
+    }
+  }
+}
+
+// Residual of eq. Rmc for one (tetrahedron, sample):
+//   r^m_Ai += int N_A rho (Hu_i + u.grad u_i) + (u.grad N_A) tau L_i
+//             + mu grad N_A . grad u_i - d_i N_A p
+//   z_Ai   += int N_A tau L_i           (receives -H per node afterwards)
+//   r^c_A  += int N_A div u + (1/rho) d_i N_A tau L_i
+// with L_i = rho (Hu_i + u.grad u_i) + d_i p and tau from eq. tau.
+__global__ void __launch_bounds__(BLK)
+k_elem_residual(DevMesh m, Phys p, const double* __restrict__ S, double* __restrict__ acc,
+                int64_t nlogical) {
+  const int64_t lb = xcd_block(nlogical);
+  if (lb < 0) return;
+  const int N = p.N;
+  const int64_t gid = lb * BLK + threadIdx.x;
+  if (gid >= m.ne * N) return;
+  const int64_t t = gid / N;
+  const int s = (int)(gid - t * N);
+  Geo G;
+  load_geo(m.geo, m.ne, t, G);
+  int64_t base[4];
+  double u[4][3], hu[4][3], pr[4];
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    const int64_t a = m.tets[A * m.ne + t];
+    base[A] = a * NCH * N + s;
+    const double* q = S + base[A];
+    u[A][0] = q[0];
+    u[A][1] = q[N];
+    u[A][2] = q[2 * N];
+    pr[A] = q[3 * N];
+    hu[A][0] = q[4 * N];
+    hu[A][1] = q[5 * N];
+    hu[A][2] = q[6 * N];
+  }
+  double Gm[3][3], gp[3], us[3], hs[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    gp[i] = 0.0;
+    us[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
+    hs[i] = hu[0][i] + hu[1][i] + hu[2][i] + hu[3][i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Gm[i][j] = 0.0;
+  }
+#pragma unroll
+  for (int A = 0; A < 4; ++A)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      gp[i] += pr[A] * G.g[A][i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Gm[i][j] += u[A][i] * G.g[A][j];
+    }
+  const double div = Gm[0][0] + Gm[1][1] + Gm[2][2];
+  const double pbar = 0.25 * (pr[0] + pr[1] + pr[2] + pr[3]);
+  const double rho = p.rho;
+  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
+  const double w = 0.25 * G.V;
+  double rm[4][3], rc[4], z[4][3], Sg[3] = {0, 0, 0};
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    rc[A] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rm[A][i] = z[A][i] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double uq[3], hq[3], adv[3], xu[3], L[3], sv[3], gal[3], c[4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      uq[i] = QB * us[i] + (QA - QB) * u[q][i];
+      hq[i] = QB * hs[i] + (QA - QB) * hu[q][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
+    xi_mul(G, uq, xu);
+    const double kap = uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + kap0;
+    const double tau = 1.0 / sqrt(kap);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      gal[i] = rho * (hq[i] + adv[i]);
+      L[i] = gal[i] + gp[i];
+      sv[i] = tau * L[i];
+      Sg[i] += w * sv[i];
+    }
+#pragma unroll
+    for (int A = 0; A < 4; ++A) c[A] = uq[0] * G.g[A][0] + uq[1] * G.g[A][1] + uq[2] * G.g[A][2];
+#pragma unroll
+    for (int A = 0; A < 4; ++A) {
+      const double NA = (A == q) ? QA : QB;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        rm[A][i] += w * (NA * gal[i] + c[A] * sv[i]);
+        z[A][i] += w * NA * sv[i];
+      }
+    }
+  }
+  const double V = G.V;
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      rm[A][i] += V * (p.mu * (G.g[A][0] * Gm[i][0] + G.g[A][1] * Gm[i][1] + G.g[A][2] * Gm[i][2])
+                       - G.g[A][i] * pbar);
+    rc[A] = w * div + (G.g[A][0] * Sg[0] + G.g[A][1] * Sg[1] + G.g[A][2] * Sg[2]) / rho;
+  }
+  scatter_rows(acc, base, N, rm, rc, z, true);
+}
+
+// Exact directional derivative of k_elem_residual along the direction
+// samples Sv (dtau = -tau^3 u.xi du from eq. tau), plus shift * int N_A N_B
+// on the velocity rows.
+__global__ void __launch_bounds__(BLK)
+k_elem_jvp_exact(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __restrict__ Sv,
+                 double* __restrict__ acc, int64_t nlogical) {
+  const int64_t lb = xcd_block(nlogical);
+  if (lb < 0) return;
+  const int N = p.N;
+  const int64_t gid = lb * BLK + threadIdx.x;
+  if (gid >= m.ne * N) return;
+  const int64_t t = gid / N;
+  const int s = (int)(gid - t * N);
+  Geo G;
+  load_geo(m.geo, m.ne, t, G);
+  int64_t base[4];
+  double u[4][3], hu[4][3], du[4][3], dhu[4][3], pr[4], dp[4];
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    const int64_t a = m.tets[A * m.ne + t];
+    base[A] = a * NCH * N + s;
+    const double* q = Sy + base[A];
+    const double* d = Sv + base[A];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u[A][i] = q[i * N];
+      hu[A][i] = q[(4 + i) * N];
+      du[A][i] = d[i * N];
+      dhu[A][i] = d[(4 + i) * N];
+    }
+    pr[A] = q[3 * N];
+    dp[A] = d[3 * N];
+  }
+  double Gm[3][3], dG[3][3], gp[3], dgp[3], us[3], hs[3], dus[3], dhs[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    gp[i] = dgp[i] = 0.0;
+    us[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
+    hs[i] = hu[0][i] + hu[1][i] + hu[2][i] + hu[3][i];
+    dus[i] = du[0][i] + du[1][i] + du[2][i] + du[3][i];
+    dhs[i] = dhu[0][i] + dhu[1][i] + dhu[2][i] + dhu[3][i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Gm[i][j] = dG[i][j] = 0.0;
+  }
+#pragma unroll
+  for (int A = 0; A < 4; ++A)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      gp[i] += pr[A] * G.g[A][i];
+      dgp[i] += dp[A] * G.g[A][i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Gm[i][j] += u[A][i] * G.g[A][j];
+        dG[i][j] += du[A][i] * G.g[A][j];
+      }
+    }
+  const double ddiv = dG[0][0] + dG[1][1] + dG[2][2];
+  const double dpbar = 0.25 * (dp[0] + dp[1] + dp[2] + dp[3]);
+  const double rho = p.rho;
+  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
+  const double w = 0.25 * G.V;
+  double rm[4][3], rc[4], z[4][3], dS[3] = {0, 0, 0};
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    rc[A] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rm[A][i] = z[A][i] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double uq[3], hq[3], duq[3], dhq[3], adv[3], dadv[3], xu[3], L[3], dL[3], sv[3], ds[3],
+        dgal[3], c[4], dc[4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      uq[i] = QB * us[i] + (QA - QB) * u[q][i];
+      hq[i] = QB * hs[i] + (QA - QB) * hu[q][i];
+      duq[i] = QB * dus[i] + (QA - QB) * du[q][i];
+      dhq[i] = QB * dhs[i] + (QA - QB) * dhu[q][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
+      dadv[i] = duq[0] * Gm[i][0] + duq[1] * Gm[i][1] + duq[2] * Gm[i][2]
+              + uq[0] * dG[i][0] + uq[1] * dG[i][1] + uq[2] * dG[i][2];
+    }
+    xi_mul(G, uq, xu);
+    const double kap = uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + kap0;
+    const double tau = 1.0 / sqrt(kap);
+    const double dtau = -tau * tau * tau * (xu[0] * duq[0] + xu[1] * duq[1] + xu[2] * duq[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      L[i] = rho * (hq[i] + adv[i]) + gp[i];
+      dgal[i] = rho * (dhq[i] + dadv[i]);
+      dL[i] = dgal[i] + dgp[i];
+      sv[i] = tau * L[i];
+      ds[i] = dtau * L[i] + tau * dL[i];
+      dS[i] += w * ds[i];
+    }
+#pragma unroll
+    for (int A = 0; A < 4; ++A) {
+      c[A] = uq[0] * G.g[A][0] + uq[1] * G.g[A][1] + uq[2] * G.g[A][2];
+      dc[A] = duq[0] * G.g[A][0] + duq[1] * G.g[A][1] + duq[2] * G.g[A][2];
+    }
+#pragma unroll
+    for (int A = 0; A < 4; ++A) {
+      const double NA = (A == q) ? QA : QB;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        rm[A][i] += w * (NA * dgal[i] + dc[A] * sv[i] + c[A] * ds[i]);
+        z[A][i] += w * NA * ds[i];
+      }
+    }
+  }
+  const double V = G.V;
+  const double ms = p.shift * V * (1.0 / 20.0);
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      rm[A][i] += V * (p.mu * (G.g[A][0] * dG[i][0] + G.g[A][1] * dG[i][1] + G.g[A][2] * dG[i][2])
+                       - G.g[A][i] * dpbar)
+                + ms * (dus[i] + du[A][i]);
+    rc[A] = w * ddiv + (G.g[A][0] * dS[0] + G.g[A][1] * dS[1] + G.g[A][2] * dS[2]) / rho;
+  }
+  scatter_rows(acc, base, N, rm, rc, z, true);
+}
+
+// The paper's tangent C + P (eqs. K_mat, ctangent) applied matrix-free:
+// advection and tau frozen at the state, stabilisation time terms dropped,
+// Galerkin time term rho int N_A H du (the F block) kept; plus shift mass.
+__global__ void __launch_bounds__(BLK)
+k_elem_jvp_paper(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __restrict__ Sv,
+                 double* __restrict__ acc, int64_t nlogical) {
+  const int64_t lb = xcd_block(nlogical);
+  if (lb < 0) return;
+  const int N = p.N;
+  const int64_t gid = lb * BLK + threadIdx.x;
+  if (gid >= m.ne * N) return;
+  const int64_t t = gid / N;
+  const int s = (int)(gid - t * N);
+  Geo G;
+  load_geo(m.geo, m.ne, t, G);
+  int64_t base[4];
+  double u[4][3], du[4][3], dhu[4][3], dp[4];
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    const int64_t a = m.tets[A * m.ne + t];
+    base[A] = a * NCH * N + s;
+    const double* q = Sy + base[A];
+    const double* d = Sv + base[A];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u[A][i] = q[i * N];
+      du[A][i] = d[i * N];
+      dhu[A][i] = d[(4 + i) * N];
+    }
+    dp[A] = d[3 * N];
+  }
+  double dG[3][3], dgp[3], us[3], dus[3], dhs[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    dgp[i] = 0.0;
+    us[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
+    dus[i] = du[0][i] + du[1][i] + du[2][i] + du[3][i];
+    dhs[i] = dhu[0][i] + dhu[1][i] + dhu[2][i] + dhu[3][i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dG[i][j] = 0.0;
+  }
+#pragma unroll
+  for (int A = 0; A < 4; ++A)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      dgp[i] += dp[A] * G.g[A][i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dG[i][j] += du[A][i] * G.g[A][j];
+    }
+  const double ddiv = dG[0][0] + dG[1][1] + dG[2][2];
+  const double dpbar = 0.25 * (dp[0] + dp[1] + dp[2] + dp[3]);
+  const double rho = p.rho;
+  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
+  const double w = 0.25 * G.V;
+  double rm[4][3], rc[4], z[4][3], dS[3] = {0, 0, 0};
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    rc[A] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rm[A][i] = z[A][i] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double uq[3], dhq[3], dadv[3], xu[3], ds[3], c[4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      uq[i] = QB * us[i] + (QA - QB) * u[q][i];
+      dhq[i] = QB * dhs[i] + (QA - QB) * dhu[q][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dadv[i] = uq[0] * dG[i][0] + uq[1] * dG[i][1] + uq[2] * dG[i][2];
+    xi_mul(G, uq, xu);
+    const double tau = 1.0 / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + kap0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      ds[i] = tau * (rho * dadv[i] + dgp[i]);
+      dS[i] += w * ds[i];
+    }
+#pragma unroll
+    for (int A = 0; A < 4; ++A) c[A] = uq[0] * G.g[A][0] + uq[1] * G.g[A][1] + uq[2] * G.g[A][2];
+#pragma unroll
+    for (int A = 0; A < 4; ++A) {
+      const double NA = (A == q) ? QA : QB;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rm[A][i] += w * (NA * rho * (dhq[i] + dadv[i]) + c[A] * ds[i]);
+    }
+  }
+  const double V = G.V;
+  const double ms = p.shift * V * (1.0 / 20.0);
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      rm[A][i] += V * (p.mu * (G.g[A][0] * dG[i][0] + G.g[A][1] * dG[i][1] + G.g[A][2] * dG[i][2])
+                       - G.g[A][i] * dpbar)
+                + ms * (dus[i] + du[A][i]);
+    rc[A] = w * ddiv + (G.g[A][0] * dS[0] + G.g[A][1] * dS[1] + G.g[A][2] * dS[2]) / rho;
+  }
+  scatter_rows(acc, base, N, rm, rc, z, false);
+}
+
+// Diagonal of P (Section 2.3: the Jacobi preconditioner): K_AA and L_AA per
+// sample, plus shift * int N_A^2 = shift V/10.  dg[a][0|1][s].
+__global__ void __launch_bounds__(BLK)
+k_elem_jacobi(DevMesh m, Phys p, const double* __restrict__ Sy, double* __restrict__ dg,
+              int64_t nlogical) {
+  const int64_t lb = xcd_block(nlogical);
+  if (lb < 0) return;
+  const int N = p.N;
+  const int64_t gid = lb * BLK + threadIdx.x;
+  if (gid >= m.ne * N) return;
+  const int64_t t = gid / N;
+  const int s = (int)(gid - t * N);
+  Geo G;
+  load_geo(m.geo, m.ne, t, G);
+  int64_t node[4];
+  double u[4][3];
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    node[A] = m.tets[A * m.ne + t];
+    const double* q = Sy + node[A] * NCH * N + s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[A][i] = q[i * N];
+  }
+  double us[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) us[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
+  const double rho = p.rho;
+  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
+  const double w = 0.25 * G.V;
+  double kd[4] = {0, 0, 0, 0}, ld[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double uq[3], xu[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) uq[i] = QB * us[i] + (QA - QB) * u[q][i];
+    xi_mul(G, uq, xu);
+    const double tau = 1.0 / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + kap0);
+#pragma unroll
+    for (int A = 0; A < 4; ++A) {
+      const double NA = (A == q) ? QA : QB;
+      const double c = uq[0] * G.g[A][0] + uq[1] * G.g[A][1] + uq[2] * G.g[A][2];
+      kd[A] += w * (rho * NA * c + rho * tau * c * c);
+      ld[A] += w * tau;
+    }
+  }
+#pragma unroll
+  for (int A = 0; A < 4; ++A) {
+    const double gg = G.g[A][0] * G.g[A][0] + G.g[A][1] * G.g[A][1] + G.g[A][2] * G.g[A][2];
+    atomic_add(dg + (node[A] * 2 + 0) * N + s, kd[A] + p.mu * G.V * gg + p.shift * G.V * 0.1);
+    atomic_add(dg + (node[A] * 2 + 1) * N + s, ld[A] * gg / rho);
+  }
+}
+
+// --------------------------------------------------------------- faces
+
+// Q[k][s] = sum over outlet k's faces of area * (mean nodal u) . n; one
+// workgroup per sample, per-outlet partial sums in LDS.
+__global__ void __launch_bounds__(BLK)
+k_outlet_flux(DevMesh m, int N, const double* __restrict__ S, double* __restrict__ Q) {
+  __shared__ double sq[64];
+  const int s = blockIdx.x;
+  for (int k = threadIdx.x; k < m.n_out; k += BLK) sq[k] = 0.0;
+  __syncthreads();
+  for (int64_t f = threadIdx.x; f < m.nof; f += BLK) {
+    double ub[3] = {0, 0, 0};
+#pragma unroll
+    for (int A = 0; A < 3; ++A) {
+      const double* q = S + (int64_t)m.of[A * m.nof + f] * NCH * N + s;
+      ub[0] += q[0];
+      ub[1] += q[N];
+      ub[2] += q[2 * N];
+    }
+    const double v = m.ofn[3 * m.nof + f] / 3.0
+                   * (ub[0] * m.ofn[f] + ub[1] * m.ofn[m.nof + f] + ub[2] * m.ofn[2 * m.nof + f]);
+    atomicAdd(&sq[m.oid[f]], v);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < m.n_out; k += BLK) Q[k * N + s] = sq[k];
+}
+
+// Outlet rows: -int N_A h n_i with h = hs - R Q, and the backflow term
+// -int N_A (rho beta/2) min(u.n, 0) u_i on the 3-point rule (Section 2.3).
+__global__ void __launch_bounds__(BLK)
+k_face_residual(DevMesh m, Phys p, const double* __restrict__ S, const double* __restrict__ hs,
+                const double* __restrict__ Rk, const double* __restrict__ Q,
+                double* __restrict__ acc) {
+  const int N = p.N;
+  const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (gid >= m.nof * N) return;
+  const int64_t f = gid / N;
+  const int s = (int)(gid - f * N);
+  const double nx = m.ofn[f], ny = m.ofn[m.nof + f], nz = m.ofn[2 * m.nof + f];
+  const double area = m.ofn[3 * m.nof + f];
+  const int k = m.oid[f];
+  double h = hs ? hs[k * N + s] : 0.0;
+  if (Rk) h -= Rk[k] * Q[k * N + s];
+  int64_t base[3];
+  double u[3][3], r[3][3];
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    base[A] = (int64_t)m.of[A * m.nof + f] * NCH * N + s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[A][i] = S[base[A] + i * N];
+    const double hn = -h * area / 3.0;
+    r[A][0] = hn * nx;
+    r[A][1] = hn * ny;
+    r[A][2] = hn * nz;
+  }
+  if (p.backflow) {
+    const double coef = -(area / 3.0) * 0.5 * p.rho * p.beta;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double uq[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        uq[i] = TRI_B * (u[0][i] + u[1][i] + u[2][i]) + (TRI_A - TRI_B) * u[q][i];
+      const double un = uq[0] * nx + uq[1] * ny + uq[2] * nz;
+      if (un < 0.0) {
+#pragma unroll
+        for (int A = 0; A < 3; ++A) {
+          const double NA = (A == q) ? TRI_A : TRI_B;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) r[A][i] += coef * un * NA * uq[i];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int A = 0; A < 3; ++A)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) atomic_add(acc + base[A] + i * N, r[A][i]);
+}
+
+// Directional derivative of k_face_residual: -int N_A (-R dQ) n_i and the
+// backflow tangent with the kink's derivative taken as zero at u.n = 0.
+__global__ void __launch_bounds__(BLK)
+k_face_jvp(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __restrict__ Sv,
+           const double* __restrict__ Rk, const double* __restrict__ dQ, double* __restrict__ acc) {
+  const int N = p.N;
+  const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (gid >= m.nof * N) return;
+  const int64_t f = gid / N;
+  const int s = (int)(gid - f * N);
+  const double nx = m.ofn[f], ny = m.ofn[m.nof + f], nz = m.ofn[2 * m.nof + f];
+  const double area = m.ofn[3 * m.nof + f];
+  const int k = m.oid[f];
+  const double dh = Rk ? -Rk[k] * dQ[k * N + s] : 0.0;
+  int64_t base[3];
+  double u[3][3], du[3][3], r[3][3];
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    base[A] = (int64_t)m.of[A * m.nof + f] * NCH * N + s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u[A][i] = Sy[base[A] + i * N];
+      du[A][i] = Sv[base[A] + i * N];
+    }
+    const double hn = -dh * area / 3.0;
+    r[A][0] = hn * nx;
+    r[A][1] = hn * ny;
+    r[A][2] = hn * nz;
+  }
+  if (p.backflow) {
+    const double coef = -(area / 3.0) * 0.5 * p.rho * p.beta;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double uq[3], duq[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        uq[i] = TRI_B * (u[0][i] + u[1][i] + u[2][i]) + (TRI_A - TRI_B) * u[q][i];
+        duq[i] = TRI_B * (du[0][i] + du[1][i] + du[2][i]) + (TRI_A - TRI_B) * du[q][i];
+      }
+      const double un = uq[0] * nx + uq[1] * ny + uq[2] * nz;
+      if (un < 0.0) {
+        const double dun = duq[0] * nx + duq[1] * ny + duq[2] * nz;
+#pragma unroll
+        for (int A = 0; A < 3; ++A) {
+          const double NA = (A == q) ? TRI_A : TRI_B;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) r[A][i] += coef * NA * (dun * uq[i] + un * duq[i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int A = 0; A < 3; ++A)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) atomic_add(acc + base[A] + i * N, r[A][i]);
+}
+
+// dg[a][c][s] -> D[c][s][a] (field-major), Dirichlet velocity rows = 1;
+// optionally dinv[a][c][s] = 1 / diag.
+__global__ void __launch_bounds__(BLK)
+k_jacobi_out(int64_t n, int N, const uint8_t* __restrict__ dmask, double* __restrict__ dg,
+             double* __restrict__ D, double* __restrict__ dinv) {
+  const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (gid >= n * 2 * N) return;
+  const int64_t a = gid / (2 * N);
+  const int r = (int)(gid - a * 2 * N);
+  const int c = r / N;
+  const int s = r - c * N;
+  double v = dg[gid];
+  if (c == 0 && dmask[a]) v = 1.0;
+  dg[gid] = v;
+  if (D) D[((int64_t)c * N + s) * n + a] = v;
+  if (dinv) dinv[gid] = 1.0 / v;
+}
+
+// -------------------------------------------------------------- vectors
+
+template <int G>
+__global__ void __launch_bounds__(BLK)
+k_dots(const double* __restrict__ Q, int64_t ld, int k0, int kc, const double* __restrict__ w,
+       int64_t L, double* __restrict__ partial, int nblk) {
+  __shared__ double red[G][BLK / 64];
+  double acc[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc[j] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < kc) acc[j] += Q[(int64_t)(k0 + j) * ld + i] * wi;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    double v = acc[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[j][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < G && threadIdx.x < kc) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < BLK / 64; ++q) v += red[threadIdx.x][q];
+    partial[(int64_t)(k0 + threadIdx.x) * nblk + blockIdx.x] = v;
+  }
+}
+
+__global__ void __launch_bounds__(BLK)
+k_reduce_rows(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+  __shared__ double red[BLK / 64];
+  const int j = blockIdx.x;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += BLK) v += partial[(int64_t)j * nblk + i];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < BLK / 64; ++q) t += red[q];
+    out[j] = t;
+  }
+}
+
+__global__ void __launch_bounds__(BLK)
+k_axpy_multi(double* __restrict__ w, const double* __restrict__ Q, int64_t ld, int k,
+             const double* __restrict__ h, double sign, int64_t L) {
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) {
+    double v = 0.0;
+    for (int j = 0; j < k; ++j) v += h[j] * Q[(int64_t)j * ld + i];
+    w[i] += sign * v;
+  }
+}
+
+__global__ void __launch_bounds__(BLK)
+k_scale(double* __restrict__ x, int64_t L, double s) {
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) x[i] *= s;
+}
+
+__global__ void __launch_bounds__(BLK)
+k_fill(double* __restrict__ x, int64_t L, double v) {
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) x[i] = v;
+}
+
+__global__ void __launch_bounds__(BLK)
+k_copy_scaled(double* __restrict__ d, const double* __restrict__ x, int64_t L, double s) {
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) d[i] = s * x[i];
+}
+
+// y[a][c][s] += s * dinv[a][c<3?0:1][s] * u[a][c][s] for c < 4, skipping the
+// velocity entries of Dirichlet nodes.  y has nch_y channels per node.
+__global__ void __launch_bounds__(BLK)
+k_mul_dinv_add(double* __restrict__ y, const double* __restrict__ u,
+               const double* __restrict__ dinv, const uint8_t* __restrict__ dmask, int64_t n,
+               int N, int nch_y, double s) {
+  const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (gid >= n * 4 * N) return;
+  const int64_t a = gid / (4 * N);
+  const int r = (int)(gid - a * 4 * N);
+  const int c = r / N;
+  const int sm = r - c * N;
+  if (c < 3 && dmask[a]) return;
+  const double d = dinv ? dinv[(a * 2 + (c < 3 ? 0 : 1)) * N + sm] : 1.0;
+  y[(a * nch_y + c) * N + sm] += s * d * u[gid];
+}
+
+__global__ void __launch_bounds__(BLK)
+k_nonfinite(const double* __restrict__ x, int64_t L, int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride)
+    bad |= !isfinite(x[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+inline unsigned tiles(int64_t n) { return (unsigned)((n + TN - 1) / TN); }
+inline unsigned blocks_for(int64_t work) { return (unsigned)((work + BLK - 1) / BLK); }
+inline unsigned stream_blocks(int64_t L) {
+  int64_t b = (L + BLK - 1) / BLK;
+  return (unsigned)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+
+hipError_t modal_to_samples(const DevMesh& m, int N, const double* Y, const double* dir,
+                            int zero_dirichlet, const double* tab, double* S, double* acc_zero,
+                            double* q_zero, int nq, hipStream_t st) {
+  if (m.n == 0) return hipSuccess;
+  const size_t lds = sizeof(double) * (4 * N * TN + 2 * N * N);
+  hipLaunchKernelGGL(k_modal_to_samples, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, Y, dir,
+                     m.dmask, zero_dirichlet, tab, S, acc_zero, q_zero, nq);
+  return hipGetLastError();
+}
+
+hipError_t samples_to_modal(const DevMesh& m, int N, const double* acc, int use_z,
+                            int zero_dir_rows, int in_ch, const double* tab, double* R,
+                            hipStream_t st) {
+  if (m.n == 0) return hipSuccess;
+  const size_t lds = sizeof(double) * (TN * in_ch * N + 2 * N * N);
+  hipLaunchKernelGGL(k_samples_to_modal, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, acc, use_z,
+                     zero_dir_rows, in_ch, m.dmask, tab, R);
+  return hipGetLastError();
+}
+
+hipError_t prepare_direction(const DevMesh& m, int N, const double* q, int in_ch,
+                             const double* dinv, int zero_dirichlet, const double* tab,
+                             double* Sv, double* acc_zero, double* q_zero, int nq,
+                             hipStream_t st) {
+  const size_t lds = sizeof(double) * (TN * 4 * N + N * N);
+  hipLaunchKernelGGL(k_prepare, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, q, in_ch, dinv,
+                     zero_dirichlet, m.dmask, tab, Sv, acc_zero, q_zero, nq);
+  return hipGetLastError();
+}
+
+hipError_t finish_rows(const DevMesh& m, int N, const double* acc, int use_z, const double* tab,
+                       const double* id_rows, double* out, hipStream_t st) {
+  const size_t lds = sizeof(double) * (TN * NCH * N + N * N);
+  hipLaunchKernelGGL(k_finish, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, acc, use_z, m.dmask,
+                     tab, id_rows, out);
+  return hipGetLastError();
+}
+
+hipError_t outlet_flux(const DevMesh& m, int N, const double* S, double* Q, hipStream_t st) {
+  if (m.nof == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_outlet_flux, dim3(N), dim3(BLK), 0, st, m, N, S, Q);
+  return hipGetLastError();
+}
+
+hipError_t elem_residual(const DevMesh& m, const Phys& p, const double* S, double* acc,
+                         hipStream_t st) {
+  const int64_t nb = (m.ne * p.N + BLK - 1) / BLK;
+  hipLaunchKernelGGL(k_elem_residual, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, S, acc, nb);
+  return hipGetLastError();
+}
+
+hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
+                          double* acc, hipStream_t st) {
+  const int64_t nb = (m.ne * p.N + BLK - 1) / BLK;
+  hipLaunchKernelGGL(k_elem_jvp_exact, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, Sy, Sv, acc,
+                     nb);
+  return hipGetLastError();
+}
+
+hipError_t elem_jvp_paper(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
+                          double* acc, hipStream_t st) {
+  const int64_t nb = (m.ne * p.N + BLK - 1) / BLK;
+  hipLaunchKernelGGL(k_elem_jvp_paper, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, Sy, Sv, acc,
+                     nb);
+  return hipGetLastError();
+}
+
+hipError_t elem_jacobi(const DevMesh& m, const Phys& p, const double* Sy, double* dg,
+                       hipStream_t st) {
+  const int64_t nb = (m.ne * p.N + BLK - 1) / BLK;
+  hipLaunchKernelGGL(k_elem_jacobi, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, Sy, dg, nb);
+  return hipGetLastError();
+}
+
+hipError_t face_residual(const DevMesh& m, const Phys& p, const double* S, const double* hs,
+                         const double* Rk, const double* Q, double* acc, hipStream_t st) {
+  if (m.nof == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_residual, dim3(blocks_for(m.nof * p.N)), dim3(BLK), 0, st, m, p, S,
+                     hs, Rk, Q, acc);
+  return hipGetLastError();
+}
+
+hipError_t face_jvp(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
+                    const double* Rk, const double* dQ, double* acc, hipStream_t st) {
+  if (m.nof == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_jvp, dim3(blocks_for(m.nof * p.N)), dim3(BLK), 0, st, m, p, Sy, Sv,
+                     Rk, dQ, acc);
+  return hipGetLastError();
+}
+
+hipError_t jacobi_out(const DevMesh& m, int N, const double* dg, double* D, double* dinv,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_out, dim3(blocks_for(m.n * 2 * N)), dim3(BLK), 0, st, m.n, N,
+                     m.dmask, const_cast<double*>(dg), D, dinv);
+  return hipGetLastError();
+}
+
+hipError_t vec_dots(const double* Q, int64_t ld, int k, const double* w, int64_t L,
+                    double* partial, int nblk, double* out, hipStream_t st) {
+  for (int k0 = 0; k0 < k; k0 += 8) {
+    const int kc = k - k0 < 8 ? k - k0 : 8;
+    hipLaunchKernelGGL(k_dots<8>, dim3(nblk), dim3(BLK), 0, st, Q, ld, k0, kc, w, L, partial,
+                       nblk);
+  }
+  hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(BLK), 0, st, partial, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t vec_axpy_multi(double* w, const double* Q, int64_t ld, int k, const double* h,
+                          double sign, int64_t L, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_multi, dim3(stream_blocks(L)), dim3(BLK), 0, st, w, Q, ld, k, h, sign,
+                     L);
+  return hipGetLastError();
+}
+
+hipError_t vec_scale(double* x, int64_t L, const double*, double s_host, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, s_host);
+  return hipGetLastError();
+}
+
+hipError_t vec_copy_scaled(double* dst, const double* src, int64_t L, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_scaled, dim3(stream_blocks(L)), dim3(BLK), 0, st, dst, src, L, s);
+  return hipGetLastError();
+}
+
+hipError_t vec_zero(double* x, int64_t L, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t vec_mul_dinv_add(double* y, const double* u, const double* dinv, const uint8_t* dmask,
+                            int64_t n, int N, int nch_y, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_mul_dinv_add, dim3(blocks_for(n * 4 * N)), dim3(BLK), 0, st, y, u, dinv,
+                     dmask, n, N, nch_y, s);
+  return hipGetLastError();
+}
+
+hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_nonfinite, dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, flag);
+  return hipGetLastError();
+}
+
+}  // namespace hb
