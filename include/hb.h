@@ -142,6 +142,13 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
 int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
               double shift, double* D, void* stream);
 
+/* Preconditioners for hb_newton_solve.  HB_PREC_JACOBI is the paper's Jacobi
+ * preconditioner diag(P) (Section 2.3).  HB_PREC_NODE_TIME keeps, for every
+ * node, the full time block of the velocity diagonal, diag_n(K_AA) +
+ * rho int N_A^2 H (the nodal diagonal block of C + P), inverted exactly; the
+ * pressure rows keep 1 / L_AA.  Both change iteration counts, not the root. */
+enum { HB_PREC_JACOBI = 0, HB_PREC_NODE_TIME = 1 };
+
 typedef struct {
   double rtol;       /* stop when ||r||_2 <= rtol * r_ref (default 1e-8)              */
   double r_ref;      /* reference norm; <= 0 means ||r(Y_in)||_2                     */
@@ -154,6 +161,9 @@ typedef struct {
   int32_t precision; /* HB_F64, or 1 = mixed (FP32 Jv and Krylov basis)               */
   int32_t jv_kind;   /* HB_JV_EXACT or HB_JV_PAPER for the Krylov operator            */
   int32_t verbose;   /* print one line per Newton step to stderr                      */
+  int32_t precond;   /* HB_PREC_JACOBI (the paper's diag(P)) or HB_PREC_NODE_TIME    */
+  double cfl_max;    /* cap of the pseudo step growth, dt <= cfl_max h_c / u_c
+                        (<= 0: no cap beyond 1e6 times the initial step)        */
 } hb_solve_opts;
 
 typedef struct {
@@ -177,6 +187,16 @@ typedef struct {
  * cases. */
 int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
                     const hb_solve_opts* opts, hb_solve_report* report, void* stream);
+
+/* Per-stage timing of hb_residual / hb_jvp for profiling.  When enabled,
+ * those calls record HIP events on their stream between stages:
+ *   0 state to samples, 1 direction to samples, 2 outlet flux,
+ *   3 element kernel, 4 outlet faces, 5 samples to modal rows.
+ * hb_last_timings waits for the last call's events and writes the stage
+ * durations in milliseconds to ms[0..5] (0 for stages a call does not
+ * run).  Returns HB_ERR_ARG if timing was not enabled for the last call. */
+int hb_set_timing(hb_mesh* mesh, int32_t enable);
+int hb_last_timings(const hb_mesh* mesh, double* ms);
 
 const char* hb_last_error(void);
 

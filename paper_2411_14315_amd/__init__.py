@@ -21,6 +21,7 @@ HB_OK, HB_ERR_ARG, HB_ERR_MESH, HB_ERR_DEVICE, HB_ERR_NOCONV, HB_ERR_NAN, HB_ERR
     0, -1, -2, -3, -4, -5, -6)
 HB_JV_EXACT, HB_JV_PAPER, HB_F64, HB_F32 = 0, 1, 0, 2
 HB_MIXED = 1
+HB_PREC_JACOBI, HB_PREC_NODE_TIME = 0, 1
 
 
 class HBError(RuntimeError):
@@ -42,7 +43,8 @@ class _Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("r_ref", C.c_double), ("gmres_eta", C.c_double),
                 ("cfl", C.c_double), ("c1", C.c_double), ("restart", C.c_int32),
                 ("max_newton", C.c_int32), ("max_gmres", C.c_int32), ("precision", C.c_int32),
-                ("jv_kind", C.c_int32), ("verbose", C.c_int32)]
+                ("jv_kind", C.c_int32), ("verbose", C.c_int32), ("precond", C.c_int32),
+                ("cfl_max", C.c_double)]
 
 
 class _Report(C.Structure):
@@ -72,9 +74,11 @@ def load():
     lib.hb_jacobi.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, dbl, vp, vp]
     lib.hb_newton_solve.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp,
                                     C.POINTER(_Opts), C.POINTER(_Report), vp]
+    lib.hb_set_timing.argtypes = [vp, i32]
+    lib.hb_last_timings.argtypes = [vp, vp]
     lib.hb_last_error.restype = C.c_char_p
     for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
-                 "hb_newton_solve"):
+                 "hb_newton_solve", "hb_set_timing", "hb_last_timings"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -126,6 +130,17 @@ class Mesh:
         keys = ("n_nodes", "n_tets", "n_dirichlet", "n_outlet_faces", "n_outlets",
                 "n_reoriented", "n_inlet", "device_bytes")
         return dict(zip(keys, map(int, out)))
+
+    def set_timing(self, enable: bool = True):
+        _check(load().hb_set_timing(self._h, 1 if enable else 0))
+
+    STAGES = ("state_to_samples", "direction_to_samples", "outlet_flux", "element",
+              "outlet_faces", "samples_to_modal")
+
+    def last_timings(self) -> dict:
+        out = np.zeros(6)
+        _check(load().hb_last_timings(self._h, out.ctypes.data))
+        return dict(zip(self.STAGES, map(float, out)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -225,10 +240,13 @@ class SolveOptions:
     precision: int = HB_F64
     jv_kind: int = HB_JV_EXACT
     verbose: int = 0
+    precond: int = HB_PREC_NODE_TIME
+    cfl_max: float = 0.0
 
     def _c(self):
         return _Opts(self.rtol, self.r_ref, self.gmres_eta, self.cfl, self.c1, self.restart,
-                     self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose)
+                     self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose,
+                     self.precond, self.cfl_max)
 
 
 def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None,

@@ -59,7 +59,7 @@ struct DevBuf {
 // Buffers that depend on the number of samples N.
 struct Workspace {
   int N = -1;
-  DevBuf Sy, Sv, acc, tab, small, dg, dinv;
+  DevBuf Sy, Sv, acc, tab, small, dg, dinv, binv;
   std::vector<double> tab_host;
   std::vector<double> bc_host;  // hs (n_out N) then R (n_out), as last uploaded
   bool bc_has_R = false;
@@ -70,16 +70,24 @@ struct Workspace {
 
 struct hb_mesh {
   DevMesh dm;
-  DevBuf tets, geo, dmask, of, ofn, oid;
+  DevBuf tets, geo, dmask, of, ofn, oid, mass;
   int64_t n_dirichlet = 0, n_reoriented = 0, n_inlet = 0;
   std::vector<int32_t> inlet_nodes;  // inlet nodes that are not wall nodes
   double mean_vol = 0.0;
   int device = 0;
   Workspace ws;
+  // stage timing (hb_set_timing)
+  bool timing = false;
+  bool timed_call = false;
+  hipEvent_t ev[7] = {};
+  ~hb_mesh() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
   size_t bytes_held() const {
     return tets.bytes + geo.bytes + dmask.bytes + of.bytes + ofn.bytes + oid.bytes + ws.Sy.bytes +
            ws.Sv.bytes + ws.acc.bytes + ws.tab.bytes + ws.small.bytes + ws.dg.bytes +
-           ws.dinv.bytes;
+           ws.dinv.bytes + ws.binv.bytes + mass.bytes;
   }
 };
 
@@ -202,6 +210,13 @@ int prepare(hb_mesh* m, const hb_params* prm, const hb_bc* bc, hipStream_t st) {
                               hipMemcpyHostToDevice, st));
   }
   return HB_OK;
+}
+
+// Stage boundary k (0..6) of a timed call.
+hipError_t mark(hb_mesh* m, int k, hipStream_t st) {
+  if (!m->timing) return hipSuccess;
+  if (k == 0) m->timed_call = true;
+  return hipEventRecord(m->ev[k], st);
 }
 
 struct Ptrs {
@@ -406,6 +421,11 @@ int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int
   HB_CHECK(m->of.ensure(sizeof(int32_t) * 3 * nof));
   HB_CHECK(m->ofn.ensure(sizeof(double) * 4 * nof));
   HB_CHECK(m->oid.ensure(sizeof(int32_t) * nof));
+  std::vector<double> massd(n_nodes, 0.0);
+  for (int64_t t = 0; t < ne; ++t)
+    for (int k = 0; k < 4; ++k) massd[T[4 * t + k]] += geo[(size_t)hb::GEO_V * ne + t] / 10.0;
+  HB_CHECK(m->mass.ensure(sizeof(double) * n_nodes));
+  HB_CHECK(hipMemcpy(m->mass.p, massd.data(), sizeof(double) * n_nodes, hipMemcpyHostToDevice));
   HB_CHECK(hipMemcpy(m->tets.p, Tsoa.data(), sizeof(int32_t) * 4 * ne, hipMemcpyHostToDevice));
   HB_CHECK(hipMemcpy(m->geo.p, geo.data(), sizeof(double) * geo.size(), hipMemcpyHostToDevice));
   HB_CHECK(hipMemcpy(m->dmask.p, dmask.data(), n_nodes, hipMemcpyHostToDevice));
@@ -425,6 +445,7 @@ int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int
   d.of = m->of.as<int32_t>();
   d.ofn = m->ofn.as<double>();
   d.oid = m->oid.as<int32_t>();
+  d.mass = m->mass.as<double>();
   for (int64_t a = 0; a < n_nodes; ++a) {
     m->n_dirichlet += dmask[a];
     m->n_inlet += inlet[a];
@@ -437,6 +458,27 @@ int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int
 }
 
 void hb_mesh_destroy(hb_mesh* mesh) { delete mesh; }
+
+int hb_set_timing(hb_mesh* m, int32_t enable) {
+  if (!m) return fail(HB_ERR_ARG, "NULL mesh");
+  if (enable && !m->ev[0])
+    for (auto& e : m->ev) HB_CHECK(hipEventCreate(&e));
+  m->timing = enable != 0;
+  m->timed_call = false;
+  return HB_OK;
+}
+
+int hb_last_timings(const hb_mesh* mesh, double* ms) {
+  if (!mesh || !ms) return fail(HB_ERR_ARG, "NULL argument");
+  if (!mesh->timing || !mesh->timed_call) return fail(HB_ERR_ARG, "no timed call");
+  HB_CHECK(hipEventSynchronize(mesh->ev[6]));
+  for (int k = 0; k < 6; ++k) {
+    float t = 0.f;
+    HB_CHECK(hipEventElapsedTime(&t, mesh->ev[k], mesh->ev[k + 1]));
+    ms[k] = t;
+  }
+  return HB_OK;
+}
 
 int hb_mesh_info(const hb_mesh* m, int64_t* info) {
   if (!m || !info) return fail(HB_ERR_ARG, "NULL argument");
@@ -463,12 +505,19 @@ int hb_residual(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, cons
   const Phys p = make_phys(prm, 0.0);
   Ptrs s = small_ptrs(m);
   const double* tab = w.tab.as<double>();
+  HB_CHECK(mark(m, 0, st));
   HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(),
                                 w.acc.as<double>(), s.Q, m->dm.n_out * N, st));
+  HB_CHECK(mark(m, 1, st));
+  HB_CHECK(mark(m, 2, st));
   if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, w.Sy.as<double>(), s.Q, st));
+  HB_CHECK(mark(m, 3, st));
   HB_CHECK(hb::elem_residual(m->dm, p, w.Sy.as<double>(), w.acc.as<double>(), st));
+  HB_CHECK(mark(m, 4, st));
   HB_CHECK(hb::face_residual(m->dm, p, w.Sy.as<double>(), s.hs, s.R, s.Q, w.acc.as<double>(), st));
+  HB_CHECK(mark(m, 5, st));
   HB_CHECK(hb::samples_to_modal(m->dm, N, w.acc.as<double>(), 1, 1, hb::NCH, tab, R, st));
+  HB_CHECK(mark(m, 6, st));
   return HB_OK;
 }
 
@@ -490,18 +539,24 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
   double* Sy = w.Sy.as<double>();
   double* Sv = w.Sv.as<double>();
   double* acc = w.acc.as<double>();
+  HB_CHECK(mark(m, 0, st));
   HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, Sy, nullptr, nullptr, 0, st));
+  HB_CHECK(mark(m, 1, st));
   HB_CHECK(hb::modal_to_samples(m->dm, N, (const double*)V, bc->dirichlet, 1, tab, Sv, acc, s.dQ,
                                 m->dm.n_out * N, st));
-  if (kind == HB_JV_EXACT) {
-    if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
+  HB_CHECK(mark(m, 2, st));
+  if (kind == HB_JV_EXACT && s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
+  HB_CHECK(mark(m, 3, st));
+  if (kind == HB_JV_EXACT)
     HB_CHECK(hb::elem_jvp_exact(m->dm, p, Sy, Sv, acc, st));
-    HB_CHECK(hb::face_jvp(m->dm, p, Sy, Sv, s.R, s.dQ, acc, st));
-    HB_CHECK(hb::samples_to_modal(m->dm, N, acc, 1, 1, hb::NCH, tab, (double*)JV, st));
-  } else {
+  else
     HB_CHECK(hb::elem_jvp_paper(m->dm, p, Sy, Sv, acc, st));
-    HB_CHECK(hb::samples_to_modal(m->dm, N, acc, 0, 1, hb::NCH, tab, (double*)JV, st));
-  }
+  HB_CHECK(mark(m, 4, st));
+  if (kind == HB_JV_EXACT) HB_CHECK(hb::face_jvp(m->dm, p, Sy, Sv, s.R, s.dQ, acc, st));
+  HB_CHECK(mark(m, 5, st));
+  HB_CHECK(hb::samples_to_modal(m->dm, N, acc, kind == HB_JV_EXACT, 1, hb::NCH, tab, (double*)JV,
+                                st));
+  HB_CHECK(mark(m, 6, st));
   return HB_OK;
 }
 
@@ -538,6 +593,7 @@ struct Solver {
   int restart;
   int nblk;
   int jv_kind;
+  const double* binv = nullptr;  // per-node time blocks, or NULL for the diagonal
   DevBuf basis, xvec, rvec, tmp, partial, hdev;
   std::vector<double> hhost;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -557,7 +613,8 @@ struct Solver {
     const double* tab = w.tab.as<double>();
     const Phys p = make_phys(prm, 0.0);
     double* Sy = w.Sy.as<double>();
-    HB_CHECK(hb::prepare_direction(m->dm, N, Sy, hb::NCH, nullptr, 0, tab, Sy, w.acc.as<double>(),
+    HB_CHECK(hb::prepare_direction(m->dm, N, Sy, hb::NCH, nullptr, nullptr, 0, tab, Sy,
+                                   w.acc.as<double>(),
                                    s.Q, m->dm.n_out * N, st));
     if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sy, s.Q, st));
     HB_CHECK(hb::elem_residual(m->dm, p, Sy, w.acc.as<double>(), st));
@@ -584,8 +641,8 @@ struct Solver {
     double* Sv = w.Sv.as<double>();
     double* acc = w.acc.as<double>();
     HB_CHECK(hipEventRecord(ev0, st));
-    HB_CHECK(hb::prepare_direction(m->dm, N, q, 4, w.dinv.as<double>(), 1, tab, Sv, acc, s.dQ,
-                                   m->dm.n_out * N, st));
+    HB_CHECK(hb::prepare_direction(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab, Sv, acc,
+                                   s.dQ, m->dm.n_out * N, st));
     if (jv_kind == HB_JV_EXACT) {
       if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
       HB_CHECK(hb::elem_jvp_exact(m->dm, p, w.Sy.as<double>(), Sv, acc, st));
@@ -726,6 +783,12 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
   HB_CHECK(S.tmp.ensure(sizeof(double) * L));
   HB_CHECK(S.partial.ensure(sizeof(double) * (size_t)(S.restart + 2) * S.nblk));
   HB_CHECK(S.hdev.ensure(sizeof(double) * (4 * (size_t)(S.restart + 1) + 8)));
+  if (opts->precond == HB_PREC_NODE_TIME) {
+    HB_CHECK(m->ws.binv.ensure(sizeof(double) * (size_t)m->dm.n * N * N));
+    S.binv = m->ws.binv.as<double>();
+  } else if (opts->precond != HB_PREC_JACOBI) {
+    return fail(HB_ERR_ARG, "unknown preconditioner");
+  }
   HB_CHECK(hipEventCreate(&S.ev0));
   HB_CHECK(hipEventCreate(&S.ev1));
   Workspace& w = m->ws;
@@ -759,6 +822,7 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
   }
   const double dt0 = uc > 0 ? opts->cfl * hc / uc : opts->cfl * hc;
   double dt = dt0;
+  const double dt_max = opts->cfl_max > 0 ? dt0 * opts->cfl_max / opts->cfl : 1e6 * dt0;
 
   DevBuf rbuf;
   HB_CHECK(rbuf.ensure(sizeof(double) * L));
@@ -783,12 +847,22 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
     HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * 2 * N, st));
     HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), st));
     HB_CHECK(hb::jacobi_out(m->dm, N, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
+    if (S.binv)
+      HB_CHECK(hb::block_factor(m->dm, N, w.dg.as<double>(), m->dm.mass, prm->rho, tab,
+                                w.binv.as<double>(), st));
     int gi = 0;
     rc = S.gmres(r, shift, opts->gmres_eta, opts->max_gmres, gi);
     if (rc) return rc;
     report->gmres_iters += gi;
-    HB_CHECK(hb::vec_mul_dinv_add(w.Sy.as<double>(), S.xvec.as<double>(), w.dinv.as<double>(),
-                                  m->dm.dmask, m->dm.n, N, hb::NCH, 1.0, st));
+    if (S.binv) {
+      HB_CHECK(hb::prepare_direction(m->dm, N, S.xvec.as<double>(), 4, w.dinv.as<double>(),
+                                     S.binv, 1, tab, w.Sv.as<double>(), nullptr, nullptr, 0, st));
+      HB_CHECK(hb::vec_mul_dinv_add(w.Sy.as<double>(), w.Sv.as<double>(), nullptr, m->dm.dmask,
+                                    m->dm.n, N, hb::NCH, hb::NCH, 1.0, st));
+    } else {
+      HB_CHECK(hb::vec_mul_dinv_add(w.Sy.as<double>(), S.xvec.as<double>(), w.dinv.as<double>(),
+                                    m->dm.dmask, m->dm.n, N, hb::NCH, 4, 1.0, st));
+    }
     double rn_new = 0.0;
     rc = S.residual(r, rn_new);
     if (rc) return rc;
@@ -796,7 +870,7 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
       report->newton_iters = it + 1;
       return fail(HB_ERR_NAN, "non-finite residual");
     }
-    dt = std::min(dt * rn / std::max(rn_new, 1e-300), 1e6 * dt0);
+    dt = std::min(dt * rn / std::max(rn_new, 1e-300), dt_max);
     rn = rn_new;
     if (opts->verbose)
       std::fprintf(stderr, "hb newton %d: |r| = %.3e  gmres %d  dt %.3e\n", it + 1, rn, gi, dt);

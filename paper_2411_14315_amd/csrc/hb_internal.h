@@ -20,6 +20,7 @@ struct DevMesh {
   const int32_t* of = nullptr;    // [3][nof] outlet triangle nodes
   const double* ofn = nullptr;    // [4][nof] unit outward normal, area
   const int32_t* oid = nullptr;   // [nof] outlet index
+  const double* mass = nullptr;   // [n] diagonal of the consistent mass, int N_A^2
 };
 
 // Per-tetrahedron geometry rows: gradients of N_1..N_3 (N_0 = -sum), volume,
@@ -76,9 +77,13 @@ hipError_t jacobi_out(const DevMesh& m, int N, const double* dg, double* D, doub
                       hipStream_t st);
 // sample-space nodal passes (Krylov path)
 hipError_t prepare_direction(const DevMesh& m, int N, const double* q, int in_ch,
-                             const double* dinv, int zero_dirichlet, const double* tab,
-                             double* Sv, double* acc_zero, double* q_zero, int nq,
-                             hipStream_t st);
+                             const double* dinv, const double* binv, int zero_dirichlet,
+                             const double* tab, double* Sv, double* acc_zero, double* q_zero,
+                             int nq, hipStream_t st);
+// Per-node time blocks diag(K_AA(s)) + rho M_AA H, inverted in place:
+// binv[a][s][k]; identity at Dirichlet nodes.
+hipError_t block_factor(const DevMesh& m, int N, const double* dg, const double* mass,
+                        double rho, const double* tab, double* binv, hipStream_t st);
 hipError_t finish_rows(const DevMesh& m, int N, const double* acc, int use_z, const double* tab,
                        const double* id_rows, double* out, hipStream_t st);
 // vectors
@@ -91,7 +96,7 @@ hipError_t vec_scale(double* x, int64_t L, const double* inv_scalar, double s_ho
 hipError_t vec_copy_scaled(double* dst, const double* src, int64_t L, double s, hipStream_t st);
 hipError_t vec_zero(double* x, int64_t L, hipStream_t st);
 hipError_t vec_mul_dinv_add(double* y, const double* u, const double* dinv, const uint8_t* dmask,
-                            int64_t n, int N, int nch_y, double s, hipStream_t st);
+                            int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st);
 hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st);
 
 }  // namespace hb

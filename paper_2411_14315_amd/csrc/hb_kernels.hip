@@ -174,16 +174,20 @@ k_samples_to_modal(int64_t n, int N, const double* __restrict__ acc, int use_z, 
   }
 }
 
-// Sample-space direction: v = dinv * q (velocity entries of Dirichlet nodes
-// zeroed if zero_dirichlet), then Sv[a][0..3] = v and Sv[a][4..6] = H v.
-// q may alias Sv when in_ch == NCH (state update in place).
+// Sample-space direction: v = P^-1 q with P^-1 the pointwise inverse
+// diagonal dinv, or for velocity the per-node time blocks binv (pressure
+// still dinv); velocity entries of Dirichlet nodes zeroed if zero_dirichlet.
+// Then Sv[a][0..3] = v and Sv[a][4..6] = H v.  q may alias Sv when
+// in_ch == NCH (state update in place).
 __global__ void __launch_bounds__(BLK)
 k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict__ dinv,
-          int zero_dirichlet, const uint8_t* __restrict__ dmask, const double* __restrict__ tab,
-          double* Sv, double* __restrict__ acc, double* __restrict__ qz, int nq) {
+          const double* __restrict__ binv, int zero_dirichlet, const uint8_t* __restrict__ dmask,
+          const double* __restrict__ tab, double* Sv, double* __restrict__ acc,
+          double* __restrict__ qz, int nq) {
   extern __shared__ double sm[];
   double* sV = sm;              // [TN][4][N]
   double* sH = sV + TN * 4 * N; // H [s][k]
+  double* sQ = sH + N * N;      // [TN][3][N] raw velocity (block path only)
   const int64_t a0 = (int64_t)blockIdx.x * TN;
   const int tn = (int)min<int64_t>(TN, n - a0);
   const int NN = N * N;
@@ -195,7 +199,11 @@ k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict
     const int s = r - c * N;
     const int64_t a = a0 + al;
     double v = q[(a * in_ch + c) * N + s];
-    if (dinv) v *= dinv[(a * 2 + (c < 3 ? 0 : 1)) * N + s];
+    if (binv && c < 3) {
+      sQ[(al * 3 + c) * N + s] = v;
+    } else if (dinv) {
+      v *= dinv[(a * 2 + (c < 3 ? 0 : 1)) * N + s];
+    }
     if (zero_dirichlet && c < 3 && dmask[a]) v = 0.0;
     sV[i] = v;
   }
@@ -206,6 +214,28 @@ k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict
   if (qz && blockIdx.x == 0)
     for (int i = threadIdx.x; i < nq; i += BLK) qz[i] = 0.0;
   __syncthreads();
+  if (binv) {
+    for (int it = threadIdx.x; it < tn * N; it += BLK) {
+      const int al = it / N;
+      const int s = it - al * N;
+      const int64_t a = a0 + al;
+      if (zero_dirichlet && dmask[a]) continue;
+      const double* row = binv + (a * N + s) * N;
+      double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+      const double* q3 = sQ + al * 3 * N;
+      for (int k = 0; k < N; ++k) {
+        const double b = row[k];
+        v0 += b * q3[k];
+        v1 += b * q3[N + k];
+        v2 += b * q3[2 * N + k];
+      }
+      double* v = sV + al * 4 * N;
+      v[s] = v0;
+      v[N + s] = v1;
+      v[2 * N + s] = v2;
+    }
+    __syncthreads();
+  }
   for (int it = threadIdx.x; it < tn * N; it += BLK) {
     const int al = it / N;
     const int s = it - al * N;
@@ -225,6 +255,39 @@ k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict
     out[4 * N] = h0;
     out[5 * N] = h1;
     out[6 * N] = h2;
+  }
+}
+
+// One thread per node: B = diag(K_AA(s)) + rho M_AA H (the time block of
+// the tangent's nodal diagonal, velocity rows), inverted in place by
+// Gauss-Jordan elimination without pivoting (B's symmetric part is the
+// positive diagonal, H being skew-symmetric).  Identity at Dirichlet nodes.
+__global__ void __launch_bounds__(BLK)
+k_block_factor(int64_t n, int N, const double* __restrict__ dg, const double* __restrict__ mass,
+               double rho, const double* __restrict__ tab, const uint8_t* __restrict__ dmask,
+               double* __restrict__ binv) {
+  const int64_t a = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (a >= n) return;
+  double* B = binv + a * N * N;
+  const double* H = tab + TAB_H * N * N;
+  const bool dir = dmask[a] != 0;
+  const double cm = rho * mass[a];
+  for (int s = 0; s < N; ++s)
+    for (int k = 0; k < N; ++k)
+      B[s * N + k] = dir ? (s == k ? 1.0 : 0.0)
+                         : cm * H[s * N + k] + (s == k ? dg[(a * 2) * N + s] : 0.0);
+  if (dir) return;
+  for (int k = 0; k < N; ++k) {
+    const double piv = B[k * N + k];
+    const double ip = 1.0 / piv;
+    B[k * N + k] = 1.0;
+    for (int j = 0; j < N; ++j) B[k * N + j] *= ip;
+    for (int i = 0; i < N; ++i) {
+      if (i == k) continue;
+      const double f = B[i * N + k];
+      B[i * N + k] = 0.0;
+      for (int j = 0; j < N; ++j) B[i * N + j] -= f * B[k * N + j];
+    }
   }
 }
 
@@ -912,7 +975,7 @@ k_copy_scaled(double* __restrict__ d, const double* __restrict__ x, int64_t L, d
 __global__ void __launch_bounds__(BLK)
 k_mul_dinv_add(double* __restrict__ y, const double* __restrict__ u,
                const double* __restrict__ dinv, const uint8_t* __restrict__ dmask, int64_t n,
-               int N, int nch_y, double s) {
+               int N, int nch_y, int nch_u, double s) {
   const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
   if (gid >= n * 4 * N) return;
   const int64_t a = gid / (4 * N);
@@ -921,7 +984,7 @@ k_mul_dinv_add(double* __restrict__ y, const double* __restrict__ u,
   const int sm = r - c * N;
   if (c < 3 && dmask[a]) return;
   const double d = dinv ? dinv[(a * 2 + (c < 3 ? 0 : 1)) * N + sm] : 1.0;
-  y[(a * nch_y + c) * N + sm] += s * d * u[gid];
+  y[(a * nch_y + c) * N + sm] += s * d * u[(a * nch_u + c) * N + sm];
 }
 
 __global__ void __launch_bounds__(BLK)
@@ -965,12 +1028,19 @@ hipError_t samples_to_modal(const DevMesh& m, int N, const double* acc, int use_
 }
 
 hipError_t prepare_direction(const DevMesh& m, int N, const double* q, int in_ch,
-                             const double* dinv, int zero_dirichlet, const double* tab,
-                             double* Sv, double* acc_zero, double* q_zero, int nq,
-                             hipStream_t st) {
-  const size_t lds = sizeof(double) * (TN * 4 * N + N * N);
+                             const double* dinv, const double* binv, int zero_dirichlet,
+                             const double* tab, double* Sv, double* acc_zero, double* q_zero,
+                             int nq, hipStream_t st) {
+  const size_t lds = sizeof(double) * (TN * 4 * N + N * N + (binv ? TN * 3 * N : 0));
   hipLaunchKernelGGL(k_prepare, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, q, in_ch, dinv,
-                     zero_dirichlet, m.dmask, tab, Sv, acc_zero, q_zero, nq);
+                     binv, zero_dirichlet, m.dmask, tab, Sv, acc_zero, q_zero, nq);
+  return hipGetLastError();
+}
+
+hipError_t block_factor(const DevMesh& m, int N, const double* dg, const double* mass,
+                        double rho, const double* tab, double* binv, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_factor, dim3(blocks_for(m.n)), dim3(BLK), 0, st, m.n, N, dg, mass,
+                     rho, tab, m.dmask, binv);
   return hipGetLastError();
 }
 
@@ -1075,9 +1145,9 @@ hipError_t vec_zero(double* x, int64_t L, hipStream_t st) {
 }
 
 hipError_t vec_mul_dinv_add(double* y, const double* u, const double* dinv, const uint8_t* dmask,
-                            int64_t n, int N, int nch_y, double s, hipStream_t st) {
+                            int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st) {
   hipLaunchKernelGGL(k_mul_dinv_add, dim3(blocks_for(n * 4 * N)), dim3(BLK), 0, st, y, u, dinv,
-                     dmask, n, N, nch_y, s);
+                     dmask, n, N, nch_y, nch_u, s);
   return hipGetLastError();
 }
 
