@@ -144,9 +144,11 @@ int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const 
 
 /* Preconditioners for hb_newton_solve.  HB_PREC_JACOBI is the paper's Jacobi
  * preconditioner diag(P) (Section 2.3).  HB_PREC_NODE_TIME keeps, for every
- * node, the full time block of the velocity diagonal, diag_n(K_AA) +
- * rho int N_A^2 H (the nodal diagonal block of C + P), inverted exactly; the
- * pressure rows keep 1 / L_AA.  Both change iteration counts, not the root. */
+ * node, the full N x N time block of the exact Jacobian's velocity diagonal:
+ * diag_n(K_AA) + rho int N_A^2 H plus the stabilisation's time terms
+ * diag(X) H - H diag(X) - rho H diag(T) H with T = int tau N_A^2 and
+ * X = int rho tau (u.grad N_A) N_A, inverted exactly per node; the pressure
+ * rows keep 1 / L_AA.  Both change iteration counts, not the root. */
 enum { HB_PREC_JACOBI = 0, HB_PREC_NODE_TIME = 1 };
 
 typedef struct {

@@ -167,7 +167,7 @@ int prepare(hb_mesh* m, const hb_params* prm, const hb_bc* bc, hipStream_t st) {
     HB_CHECK(w.Sy.ensure(sizeof(double) * n * hb::NCH * N));
     HB_CHECK(w.Sv.ensure(sizeof(double) * n * hb::NCH * N));
     HB_CHECK(w.acc.ensure(sizeof(double) * n * hb::NCH * N));
-    HB_CHECK(w.dg.ensure(sizeof(double) * n * 2 * N));
+    HB_CHECK(w.dg.ensure(sizeof(double) * n * 4 * N));
     HB_CHECK(w.dinv.ensure(sizeof(double) * n * 2 * N));
     HB_CHECK(w.tab.ensure(sizeof(double) * hb::TAB_COUNT * N * N));
     // small: Q, dQ, hs (n_out N each), R (n_out), flag
@@ -575,8 +575,8 @@ int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const 
   HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(), nullptr,
                                 nullptr, 0, st));
   HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * 2 * N, st));
-  HB_CHECK(hb::elem_jacobi(m->dm, p, w.Sy.as<double>(), w.dg.as<double>(), st));
-  HB_CHECK(hb::jacobi_out(m->dm, N, w.dg.as<double>(), D, nullptr, st));
+  HB_CHECK(hb::elem_jacobi(m->dm, p, w.Sy.as<double>(), w.dg.as<double>(), 0, st));
+  HB_CHECK(hb::jacobi_out(m->dm, N, 2, w.dg.as<double>(), D, nullptr, st));
   return HB_OK;
 }
 
@@ -844,9 +844,10 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
     if (it >= opts->max_newton) break;
     const double shift = opts->c1 * prm->rho / dt;
     const Phys pj = make_phys(prm, shift);
-    HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * 2 * N, st));
-    HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), st));
-    HB_CHECK(hb::jacobi_out(m->dm, N, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
+    const int nc = S.binv ? 4 : 2;
+    HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * nc * N, st));
+    HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), S.binv ? 1 : 0, st));
+    HB_CHECK(hb::jacobi_out(m->dm, N, nc, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
     if (S.binv)
       HB_CHECK(hb::block_factor(m->dm, N, w.dg.as<double>(), m->dm.mass, prm->rho, tab,
                                 w.binv.as<double>(), st));

@@ -68,20 +68,21 @@ hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const double* Sy, con
 hipError_t elem_jvp_paper(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
                           double* acc, hipStream_t st);
 hipError_t elem_jacobi(const DevMesh& m, const Phys& p, const double* Sy, double* dg,
-                       hipStream_t st);
+                       int time_terms, hipStream_t st);
 hipError_t face_residual(const DevMesh& m, const Phys& p, const double* S, const double* hs,
                          const double* Rk, const double* Q, double* acc, hipStream_t st);
 hipError_t face_jvp(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
                     const double* Rk, const double* dQ, double* acc, hipStream_t st);
-hipError_t jacobi_out(const DevMesh& m, int N, const double* dg, double* D, double* dinv,
+hipError_t jacobi_out(const DevMesh& m, int N, int nc, const double* dg, double* D, double* dinv,
                       hipStream_t st);
 // sample-space nodal passes (Krylov path)
 hipError_t prepare_direction(const DevMesh& m, int N, const double* q, int in_ch,
                              const double* dinv, const double* binv, int zero_dirichlet,
                              const double* tab, double* Sv, double* acc_zero, double* q_zero,
                              int nq, hipStream_t st);
-// Per-node time blocks diag(K_AA(s)) + rho M_AA H, inverted in place:
-// binv[a][s][k]; identity at Dirichlet nodes.
+// Per-node velocity time blocks of the exact Jacobian's nodal diagonal,
+// inverted in place: binv[a][s][k]; identity at Dirichlet nodes; dg with
+// 4 channels (K, L, T, X) from elem_jacobi(time_terms = 1).
 hipError_t block_factor(const DevMesh& m, int N, const double* dg, const double* mass,
                         double rho, const double* tab, double* binv, hipStream_t st);
 hipError_t finish_rows(const DevMesh& m, int N, const double* acc, int use_z, const double* tab,

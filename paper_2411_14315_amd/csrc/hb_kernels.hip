@@ -258,10 +258,15 @@ k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict
   }
 }
 
-// One thread per node: B = diag(K_AA(s)) + rho M_AA H (the time block of
-// the tangent's nodal diagonal, velocity rows), inverted in place by
-// Gauss-Jordan elimination without pivoting (B's symmetric part is the
-// positive diagonal, H being skew-symmetric).  Identity at Dirichlet nodes.
+// One thread per node: the velocity block of the exact Jacobian's nodal
+// diagonal in time,
+//   B = diag(K_AA) + rho M_AA H + diag(X_AA) H - H diag(X_AA) - rho H diag(T_AA) H
+// (Galerkin time term, and the stabilisation's time terms: the test
+// function's -H N_A against tau L, with L's rho H u and rho u.grad u, and
+// the streamline test against tau rho H u), inverted in place by
+// Gauss-Jordan elimination without pivoting (the symmetric part of B is
+// diag(K_AA) + rho H^T diag(T_AA) H, positive).  Identity at Dirichlet
+// nodes.  dg has 4 channels (K, L, T, X).
 __global__ void __launch_bounds__(BLK)
 k_block_factor(int64_t n, int N, const double* __restrict__ dg, const double* __restrict__ mass,
                double rho, const double* __restrict__ tab, const uint8_t* __restrict__ dmask,
@@ -272,10 +277,22 @@ k_block_factor(int64_t n, int N, const double* __restrict__ dg, const double* __
   const double* H = tab + TAB_H * N * N;
   const bool dir = dmask[a] != 0;
   const double cm = rho * mass[a];
+  const double* Kd = dg + (a * 4) * N;
+  const double* Td = Kd + 2 * N;
+  const double* Xd = Kd + 3 * N;
   for (int s = 0; s < N; ++s)
-    for (int k = 0; k < N; ++k)
-      B[s * N + k] = dir ? (s == k ? 1.0 : 0.0)
-                         : cm * H[s * N + k] + (s == k ? dg[(a * 2) * N + s] : 0.0);
+    for (int k = 0; k < N; ++k) {
+      if (dir) {
+        B[s * N + k] = (s == k) ? 1.0 : 0.0;
+        continue;
+      }
+      double v = (cm + Xd[s]) * H[s * N + k] - H[s * N + k] * Xd[k];
+      double h2 = 0.0;
+      for (int t = 0; t < N; ++t) h2 += H[s * N + t] * Td[t] * H[t * N + k];
+      v -= rho * h2;
+      if (s == k) v += Kd[s];
+      B[s * N + k] = v;
+    }
   if (dir) return;
   for (int k = 0; k < N; ++k) {
     const double piv = B[k * N + k];
@@ -682,10 +699,13 @@ k_elem_jvp_paper(DevMesh m, Phys p, const double* __restrict__ Sy, const double*
 }
 
 // Diagonal of P (Section 2.3: the Jacobi preconditioner): K_AA and L_AA per
-// sample, plus shift * int N_A^2 = shift V/10.  dg[a][0|1][s].
+// sample, plus shift * int N_A^2 = shift V/10.  dg[a][0|1][s].  With
+// time_terms, also the nodal integrals that the exact Jacobian's
+// stabilisation time terms multiply: T_AA = int tau N_A^2 in dg[a][2][s]
+// and X_AA = int rho tau (u.grad N_A) N_A in dg[a][3][s] (dg has 4 channels).
 __global__ void __launch_bounds__(BLK)
 k_elem_jacobi(DevMesh m, Phys p, const double* __restrict__ Sy, double* __restrict__ dg,
-              int64_t nlogical) {
+              int time_terms, int64_t nlogical) {
   const int64_t lb = xcd_block(nlogical);
   if (lb < 0) return;
   const int N = p.N;
@@ -710,7 +730,7 @@ k_elem_jacobi(DevMesh m, Phys p, const double* __restrict__ Sy, double* __restri
   const double rho = p.rho;
   const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
   const double w = 0.25 * G.V;
-  double kd[4] = {0, 0, 0, 0}, ld[4] = {0, 0, 0, 0};
+  double kd[4] = {0, 0, 0, 0}, ld[4] = {0, 0, 0, 0}, td[4] = {0, 0, 0, 0}, xd[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     double uq[3], xu[3];
@@ -724,13 +744,21 @@ k_elem_jacobi(DevMesh m, Phys p, const double* __restrict__ Sy, double* __restri
       const double c = uq[0] * G.g[A][0] + uq[1] * G.g[A][1] + uq[2] * G.g[A][2];
       kd[A] += w * (rho * NA * c + rho * tau * c * c);
       ld[A] += w * tau;
+      td[A] += w * tau * NA * NA;
+      xd[A] += w * rho * tau * c * NA;
     }
   }
+  const int nc = time_terms ? 4 : 2;
 #pragma unroll
   for (int A = 0; A < 4; ++A) {
     const double gg = G.g[A][0] * G.g[A][0] + G.g[A][1] * G.g[A][1] + G.g[A][2] * G.g[A][2];
-    atomic_add(dg + (node[A] * 2 + 0) * N + s, kd[A] + p.mu * G.V * gg + p.shift * G.V * 0.1);
-    atomic_add(dg + (node[A] * 2 + 1) * N + s, ld[A] * gg / rho);
+    double* d = dg + (node[A] * nc) * N + s;
+    atomic_add(d, kd[A] + p.mu * G.V * gg + p.shift * G.V * 0.1);
+    atomic_add(d + N, ld[A] * gg / rho);
+    if (time_terms) {
+      atomic_add(d + 2 * N, td[A]);
+      atomic_add(d + 3 * N, xd[A]);
+    }
   }
 }
 
@@ -874,7 +902,7 @@ k_face_jvp(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __res
 // dg[a][c][s] -> D[c][s][a] (field-major), Dirichlet velocity rows = 1;
 // optionally dinv[a][c][s] = 1 / diag.
 __global__ void __launch_bounds__(BLK)
-k_jacobi_out(int64_t n, int N, const uint8_t* __restrict__ dmask, double* __restrict__ dg,
+k_jacobi_out(int64_t n, int N, int nc, const uint8_t* __restrict__ dmask, double* __restrict__ dg,
              double* __restrict__ D, double* __restrict__ dinv) {
   const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
   if (gid >= n * 2 * N) return;
@@ -882,9 +910,10 @@ k_jacobi_out(int64_t n, int N, const uint8_t* __restrict__ dmask, double* __rest
   const int r = (int)(gid - a * 2 * N);
   const int c = r / N;
   const int s = r - c * N;
-  double v = dg[gid];
+  double* d = dg + (a * nc + c) * N + s;
+  double v = *d;
   if (c == 0 && dmask[a]) v = 1.0;
-  dg[gid] = v;
+  *d = v;
   if (D) D[((int64_t)c * N + s) * n + a] = v;
   if (dinv) dinv[gid] = 1.0 / v;
 }
@@ -1082,9 +1111,10 @@ hipError_t elem_jvp_paper(const DevMesh& m, const Phys& p, const double* Sy, con
 }
 
 hipError_t elem_jacobi(const DevMesh& m, const Phys& p, const double* Sy, double* dg,
-                       hipStream_t st) {
+                       int time_terms, hipStream_t st) {
   const int64_t nb = (m.ne * p.N + BLK - 1) / BLK;
-  hipLaunchKernelGGL(k_elem_jacobi, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, Sy, dg, nb);
+  hipLaunchKernelGGL(k_elem_jacobi, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, Sy, dg,
+                     time_terms, nb);
   return hipGetLastError();
 }
 
@@ -1104,9 +1134,9 @@ hipError_t face_jvp(const DevMesh& m, const Phys& p, const double* Sy, const dou
   return hipGetLastError();
 }
 
-hipError_t jacobi_out(const DevMesh& m, int N, const double* dg, double* D, double* dinv,
+hipError_t jacobi_out(const DevMesh& m, int N, int nc, const double* dg, double* D, double* dinv,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_out, dim3(blocks_for(m.n * 2 * N)), dim3(BLK), 0, st, m.n, N,
+  hipLaunchKernelGGL(k_jacobi_out, dim3(blocks_for(m.n * 2 * N)), dim3(BLK), 0, st, m.n, N, nc,
                      m.dmask, const_cast<double*>(dg), D, dinv);
   return hipGetLastError();
 }
