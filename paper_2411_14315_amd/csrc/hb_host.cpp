@@ -68,8 +68,14 @@ struct Workspace {
 
 }  // namespace
 
+struct BlockMap {
+  hb::ElemBlocks eb;
+  DevBuf ptr, nodes, slot;
+};
+
 struct hb_mesh {
   DevMesh dm;
+  BlockMap bmaps[4];  // element blocks of 32, 16, 8 and 4 tetrahedra
   DevBuf tets, geo, dmask, of, ofn, oid, mass;
   int64_t n_dirichlet = 0, n_reoriented = 0, n_inlet = 0;
   std::vector<int32_t> inlet_nodes;  // inlet nodes that are not wall nodes
@@ -87,7 +93,10 @@ struct hb_mesh {
   size_t bytes_held() const {
     return tets.bytes + geo.bytes + dmask.bytes + of.bytes + ofn.bytes + oid.bytes + ws.Sy.bytes +
            ws.Sv.bytes + ws.acc.bytes + ws.tab.bytes + ws.small.bytes + ws.dg.bytes +
-           ws.dinv.bytes + ws.binv.bytes + mass.bytes;
+           ws.dinv.bytes + ws.binv.bytes + mass.bytes + bmaps[0].ptr.bytes + bmaps[0].nodes.bytes +
+           bmaps[0].slot.bytes + bmaps[1].ptr.bytes + bmaps[1].nodes.bytes + bmaps[1].slot.bytes +
+           bmaps[2].ptr.bytes + bmaps[2].nodes.bytes + bmaps[2].slot.bytes + bmaps[3].ptr.bytes +
+           bmaps[3].nodes.bytes + bmaps[3].slot.bytes;
   }
 };
 
@@ -238,6 +247,51 @@ Ptrs small_ptrs(hb_mesh* m) {
   p.R = m->ws.bc_has_R ? b + 3 * (size_t)nout * N : nullptr;
   p.flag = reinterpret_cast<int*>(b + 3 * (size_t)nout * N + nout);
   return p;
+}
+
+// Largest element block whose LDS accumulator (unique nodes x 7 x N
+// doubles) stays within 64 KiB, so that two or more workgroups fit per CU.
+const hb::ElemBlocks& pick_blocks(const hb_mesh* m, int N) {
+  for (const auto& b : m->bmaps)
+    if ((size_t)b.eb.max_unique * hb::NCH * N * sizeof(double) <= 64 * 1024) return b.eb;
+  return m->bmaps[3].eb;
+}
+
+// Unique nodes of each run of `size` consecutive tetrahedra and the slot of
+// every element node among them.
+int build_blocks(BlockMap& bm, const std::vector<int32_t>& T, int64_t ne, int size) {
+  const int64_t nb = (ne + size - 1) / size;
+  std::vector<int32_t> ptr(nb + 1, 0), nodes;
+  std::vector<uint8_t> slot(4 * ne);
+  nodes.reserve(ne * 2);
+  int maxu = 0;
+  std::vector<int32_t> u;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t e0 = b * size, e1 = std::min<int64_t>(ne, e0 + size);
+    u.assign(T.begin() + 4 * e0, T.begin() + 4 * e1);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    for (int64_t t = e0; t < e1; ++t)
+      for (int A = 0; A < 4; ++A)
+        slot[A * ne + t] =
+            (uint8_t)(std::lower_bound(u.begin(), u.end(), T[4 * t + A]) - u.begin());
+    nodes.insert(nodes.end(), u.begin(), u.end());
+    ptr[b + 1] = (int32_t)nodes.size();
+    maxu = std::max<int>(maxu, (int)u.size());
+  }
+  HB_CHECK(bm.ptr.ensure(sizeof(int32_t) * ptr.size()));
+  HB_CHECK(bm.nodes.ensure(sizeof(int32_t) * nodes.size()));
+  HB_CHECK(bm.slot.ensure(slot.size()));
+  HB_CHECK(hipMemcpy(bm.ptr.p, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice));
+  HB_CHECK(hipMemcpy(bm.nodes.p, nodes.data(), sizeof(int32_t) * nodes.size(),
+                     hipMemcpyHostToDevice));
+  HB_CHECK(hipMemcpy(bm.slot.p, slot.data(), slot.size(), hipMemcpyHostToDevice));
+  bm.eb.size = size;
+  bm.eb.max_unique = maxu;
+  bm.eb.ptr = bm.ptr.as<int32_t>();
+  bm.eb.nodes = bm.nodes.as<int32_t>();
+  bm.eb.slot = bm.slot.as<uint8_t>();
+  return HB_OK;
 }
 
 }  // namespace
@@ -446,6 +500,13 @@ int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int
   d.ofn = m->ofn.as<double>();
   d.oid = m->oid.as<int32_t>();
   d.mass = m->mass.as<double>();
+  {
+    const int sizes[4] = {32, 16, 8, 4};
+    for (int i = 0; i < 4; ++i) {
+      const int rc = build_blocks(m->bmaps[i], T, ne, sizes[i]);
+      if (rc) return rc;
+    }
+  }
   for (int64_t a = 0; a < n_nodes; ++a) {
     m->n_dirichlet += dmask[a];
     m->n_inlet += inlet[a];
@@ -512,7 +573,8 @@ int hb_residual(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, cons
   HB_CHECK(mark(m, 2, st));
   if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, w.Sy.as<double>(), s.Q, st));
   HB_CHECK(mark(m, 3, st));
-  HB_CHECK(hb::elem_residual(m->dm, p, w.Sy.as<double>(), w.acc.as<double>(), st));
+  HB_CHECK(hb::elem_residual(m->dm, p, w.Sy.as<double>(), w.acc.as<double>(),
+                             pick_blocks(m, N), st));
   HB_CHECK(mark(m, 4, st));
   HB_CHECK(hb::face_residual(m->dm, p, w.Sy.as<double>(), s.hs, s.R, s.Q, w.acc.as<double>(), st));
   HB_CHECK(mark(m, 5, st));
@@ -548,7 +610,7 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
   if (kind == HB_JV_EXACT && s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
   HB_CHECK(mark(m, 3, st));
   if (kind == HB_JV_EXACT)
-    HB_CHECK(hb::elem_jvp_exact(m->dm, p, Sy, Sv, acc, st));
+    HB_CHECK(hb::elem_jvp_exact(m->dm, p, Sy, Sv, acc, pick_blocks(m, N), st));
   else
     HB_CHECK(hb::elem_jvp_paper(m->dm, p, Sy, Sv, acc, st));
   HB_CHECK(mark(m, 4, st));
@@ -617,7 +679,7 @@ struct Solver {
                                    w.acc.as<double>(),
                                    s.Q, m->dm.n_out * N, st));
     if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sy, s.Q, st));
-    HB_CHECK(hb::elem_residual(m->dm, p, Sy, w.acc.as<double>(), st));
+    HB_CHECK(hb::elem_residual(m->dm, p, Sy, w.acc.as<double>(), pick_blocks(m, N), st));
     HB_CHECK(hb::face_residual(m->dm, p, Sy, s.hs, s.R, s.Q, w.acc.as<double>(), st));
     HB_CHECK(hb::finish_rows(m->dm, N, w.acc.as<double>(), 1, tab, nullptr, r, st));
     return norm(r, nrm);
@@ -645,7 +707,7 @@ struct Solver {
                                    s.dQ, m->dm.n_out * N, st));
     if (jv_kind == HB_JV_EXACT) {
       if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
-      HB_CHECK(hb::elem_jvp_exact(m->dm, p, w.Sy.as<double>(), Sv, acc, st));
+      HB_CHECK(hb::elem_jvp_exact(m->dm, p, w.Sy.as<double>(), Sv, acc, pick_blocks(m, N), st));
       HB_CHECK(hb::face_jvp(m->dm, p, w.Sy.as<double>(), Sv, s.R, s.dQ, acc, st));
       HB_CHECK(hb::finish_rows(m->dm, N, acc, 1, tab, q, wout, st));
     } else {

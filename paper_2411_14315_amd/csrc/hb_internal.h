@@ -23,6 +23,17 @@ struct DevMesh {
   const double* mass = nullptr;   // [n] diagonal of the consistent mass, int N_A^2
 };
 
+// Element blocks for workgroup-level accumulation: consecutive runs of
+// `size` tetrahedra, the unique nodes of each run, and every element node's
+// slot among them.
+struct ElemBlocks {
+  int32_t size = 0;
+  int32_t max_unique = 0;
+  const int32_t* ptr = nullptr;    // [n_blocks + 1] offsets into nodes
+  const int32_t* nodes = nullptr;  // unique nodes of each block
+  const uint8_t* slot = nullptr;   // [4][ne] slot of element node A in its block
+};
+
 // Per-tetrahedron geometry rows: gradients of N_1..N_3 (N_0 = -sum), volume,
 // the upper triangle of xi = J^-T J^-1 and xi:xi.
 enum {
@@ -62,9 +73,9 @@ hipError_t samples_to_modal(const DevMesh& m, int N, const double* acc, int use_
                             hipStream_t st);
 hipError_t outlet_flux(const DevMesh& m, int N, const double* S, double* Q, hipStream_t st);
 hipError_t elem_residual(const DevMesh& m, const Phys& p, const double* S, double* acc,
-                         hipStream_t st);
+                         const ElemBlocks& eb, hipStream_t st);
 hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
-                          double* acc, hipStream_t st);
+                          double* acc, const ElemBlocks& eb, hipStream_t st);
 hipError_t elem_jvp_paper(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
                           double* acc, hipStream_t st);
 hipError_t elem_jacobi(const DevMesh& m, const Phys& p, const double* Sy, double* dg,

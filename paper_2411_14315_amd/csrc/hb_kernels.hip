@@ -7,11 +7,14 @@
 //   node tiles   modal <-> time-sample transforms and H products, one small
 //                dense N x N contraction per node and field, staged through
 //                LDS so that every global access is a contiguous run;
-//   elements     one lane per (tetrahedron, sample): gather the four nodes'
-//                samples, evaluate the Galerkin and GLS terms at the 4-point
-//                quadrature, scatter the 4 x 7 node rows with hardware FP64
-//                atomics; workgroups are mapped so that each XCD (own L2)
-//                walks a contiguous range of elements;
+//   elements     one quad of four lanes per (tetrahedron, sample) for the
+//                residual and exact Jacobian-vector kernels (lane A holds
+//                node A and quadrature point A; element sums and the row
+//                scatter go through quad shuffles, then 7 FP64 hardware
+//                atomics per lane); one lane per (tetrahedron, sample) for
+//                the paper tangent and the Jacobi diagonal; workgroups are
+//                mapped so that each XCD (own L2) walks a contiguous range
+//                of elements;
 //   faces        one lane per (outlet triangle, sample): traction,
 //                resistance and backflow terms.
 //
@@ -364,237 +367,242 @@ __device__ __forceinline__ void scatter_rows(double* __restrict__ acc, const int
   }
 }
 
+// Quad-lane element kernels: one (tetrahedron, sample) is spread over the
+// four lanes of a quad, lane A holding node A and quadrature point A of the
+// 4-point rule (its barycentric weights are QA at node A and QB at the
+// others).  Element-constant sums are all-reduced across the quad; each
+// lane forms its quadrature point's contributions to the rows of all four
+// nodes; a reduce-scatter across the quad leaves lane A with node A's seven
+// rows, which it adds to the accumulator with seven atomics.
+
+__device__ __forceinline__ double quad_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  return v;
+}
+
+// cr[B][c] (contributions of this lane to node B, channel c) -> the sum
+// over the quad of cr[A][c] for this lane's A.
+__device__ __forceinline__ void quad_reduce_scatter(int A, double cr[4][NCH], double out[NCH]) {
+  const bool hi = (A & 2) != 0, lo = (A & 1) != 0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const double k0 = hi ? cr[2][c] : cr[0][c];
+    const double k1 = hi ? cr[3][c] : cr[1][c];
+    const double s0 = hi ? cr[0][c] : cr[2][c];
+    const double s1 = hi ? cr[1][c] : cr[3][c];
+    const double r0 = k0 + __shfl_xor(s0, 2);
+    const double r1 = k1 + __shfl_xor(s1, 2);
+    out[c] = (lo ? r1 : r0) + __shfl_xor(lo ? r0 : r1, 1);
+  }
+}
+
+__device__ __forceinline__ void pick_grad(const Geo& G, int A, double g[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    g[i] = A == 0 ? G.g[0][i] : A == 1 ? G.g[1][i] : A == 2 ? G.g[2][i] : G.g[3][i];
+}
+
 // Residual of eq. Rmc for one (tetrahedron, sample):
 //   r^m_Ai += int N_A rho (Hu_i + u.grad u_i) + (u.grad N_A) tau L_i
 //             + mu grad N_A . grad u_i - d_i N_A p
 //   z_Ai   += int N_A tau L_i           (receives -H per node afterwards)
 //   r^c_A  += int N_A div u + (1/rho) d_i N_A tau L_i
 // with L_i = rho (Hu_i + u.grad u_i) + d_i p and tau from eq. tau.
-__global__ void __launch_bounds__(BLK)
-k_elem_residual(DevMesh m, Phys p, const double* __restrict__ S, double* __restrict__ acc,
-                int64_t nlogical) {
-  const int64_t lb = xcd_block(nlogical);
-  if (lb < 0) return;
+// Lane body: this lane's node row values (7 channels) for element t, sample
+// s, node/quadrature index A; returns the node's accumulator offset.
+__device__ __forceinline__ int64_t residual_lane(const DevMesh& m, const Phys& p,
+                                                 const double* __restrict__ S, int64_t t, int s,
+                                                 int A, double res[NCH]) {
   const int N = p.N;
-  const int64_t gid = lb * BLK + threadIdx.x;
-  if (gid >= m.ne * N) return;
-  const int64_t t = gid / N;
-  const int s = (int)(gid - t * N);
   Geo G;
   load_geo(m.geo, m.ne, t, G);
-  int64_t base[4];
-  double u[4][3], hu[4][3], pr[4];
-#pragma unroll
-  for (int A = 0; A < 4; ++A) {
-    const int64_t a = m.tets[A * m.ne + t];
-    base[A] = a * NCH * N + s;
-    const double* q = S + base[A];
-    u[A][0] = q[0];
-    u[A][1] = q[N];
-    u[A][2] = q[2 * N];
-    pr[A] = q[3 * N];
-    hu[A][0] = q[4 * N];
-    hu[A][1] = q[5 * N];
-    hu[A][2] = q[6 * N];
-  }
-  double Gm[3][3], gp[3], us[3], hs[3];
+  double gA[3];
+  pick_grad(G, A, gA);
+  const int64_t base = (int64_t)m.tets[A * m.ne + t] * NCH * N + s;
+  const double* q = S + base;
+  double u[3], hu[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    gp[i] = 0.0;
-    us[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
-    hs[i] = hu[0][i] + hu[1][i] + hu[2][i] + hu[3][i];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) Gm[i][j] = 0.0;
+    u[i] = q[i * N];
+    hu[i] = q[(4 + i) * N];
   }
+  const double pr = q[3 * N];
+  double Gm[3][3], gp[3], uq[3], hq[3];
 #pragma unroll
-  for (int A = 0; A < 4; ++A)
+  for (int i = 0; i < 3; ++i) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      gp[i] += pr[A] * G.g[A][i];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) Gm[i][j] += u[A][i] * G.g[A][j];
-    }
-  const double div = Gm[0][0] + Gm[1][1] + Gm[2][2];
-  const double pbar = 0.25 * (pr[0] + pr[1] + pr[2] + pr[3]);
+    for (int j = 0; j < 3; ++j) Gm[i][j] = quad_sum(u[i] * gA[j]);
+    gp[i] = quad_sum(pr * gA[i]);
+    uq[i] = QB * quad_sum(u[i]) + (QA - QB) * u[i];
+    hq[i] = QB * quad_sum(hu[i]) + (QA - QB) * hu[i];
+  }
+  const double pbar = 0.25 * quad_sum(pr);
   const double rho = p.rho;
-  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
   const double w = 0.25 * G.V;
-  double rm[4][3], rc[4], z[4][3], Sg[3] = {0, 0, 0};
+  double adv[3], xu[3], sv[3], gal[3];
 #pragma unroll
-  for (int A = 0; A < 4; ++A) {
-    rc[A] = 0.0;
+  for (int i = 0; i < 3; ++i) adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
+  xi_mul(G, uq, xu);
+  const double tau =
+      1.0 / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + p.C_I * p.nu * p.nu * G.xixi);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) rm[A][i] = z[A][i] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    gal[i] = rho * (hq[i] + adv[i]);
+    sv[i] = tau * (gal[i] + gp[i]);
   }
+  double cr[4][NCH];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double uq[3], hq[3], adv[3], xu[3], L[3], sv[3], gal[3], c[4];
+  for (int B = 0; B < 4; ++B) {
+    const double NB = (B == A) ? QA : QB;
+    const double c = uq[0] * G.g[B][0] + uq[1] * G.g[B][1] + uq[2] * G.g[B][2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      uq[i] = QB * us[i] + (QA - QB) * u[q][i];
-      hq[i] = QB * hs[i] + (QA - QB) * hu[q][i];
+      cr[B][i] = w * (NB * gal[i] + c * sv[i]);
+      cr[B][4 + i] = w * NB * sv[i];
     }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
-    xi_mul(G, uq, xu);
-    const double kap = uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + kap0;
-    const double tau = 1.0 / sqrt(kap);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      gal[i] = rho * (hq[i] + adv[i]);
-      L[i] = gal[i] + gp[i];
-      sv[i] = tau * L[i];
-      Sg[i] += w * sv[i];
-    }
-#pragma unroll
-    for (int A = 0; A < 4; ++A) c[A] = uq[0] * G.g[A][0] + uq[1] * G.g[A][1] + uq[2] * G.g[A][2];
-#pragma unroll
-    for (int A = 0; A < 4; ++A) {
-      const double NA = (A == q) ? QA : QB;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        rm[A][i] += w * (NA * gal[i] + c[A] * sv[i]);
-        z[A][i] += w * NA * sv[i];
-      }
-    }
+    cr[B][3] = w * (G.g[B][0] * sv[0] + G.g[B][1] * sv[1] + G.g[B][2] * sv[2]) / rho;
   }
+  quad_reduce_scatter(A, cr, res);
   const double V = G.V;
 #pragma unroll
-  for (int A = 0; A < 4; ++A) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      rm[A][i] += V * (p.mu * (G.g[A][0] * Gm[i][0] + G.g[A][1] * Gm[i][1] + G.g[A][2] * Gm[i][2])
-                       - G.g[A][i] * pbar);
-    rc[A] = w * div + (G.g[A][0] * Sg[0] + G.g[A][1] * Sg[1] + G.g[A][2] * Sg[2]) / rho;
-  }
-  scatter_rows(acc, base, N, rm, rc, z, true);
+  for (int i = 0; i < 3; ++i)
+    res[i] += V * (p.mu * (gA[0] * Gm[i][0] + gA[1] * Gm[i][1] + gA[2] * Gm[i][2]) - gA[i] * pbar);
+  res[3] += w * (Gm[0][0] + Gm[1][1] + Gm[2][2]);
+  return base;
 }
 
 // Exact directional derivative of k_elem_residual along the direction
 // samples Sv (dtau = -tau^3 u.xi du from eq. tau), plus shift * int N_A N_B
 // on the velocity rows.
-__global__ void __launch_bounds__(BLK)
-k_elem_jvp_exact(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __restrict__ Sv,
-                 double* __restrict__ acc, int64_t nlogical) {
-  const int64_t lb = xcd_block(nlogical);
-  if (lb < 0) return;
+__device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& p,
+                                                  const double* __restrict__ Sy,
+                                                  const double* __restrict__ Sv, int64_t t, int s,
+                                                  int A, double res[NCH]) {
   const int N = p.N;
-  const int64_t gid = lb * BLK + threadIdx.x;
-  if (gid >= m.ne * N) return;
-  const int64_t t = gid / N;
-  const int s = (int)(gid - t * N);
   Geo G;
   load_geo(m.geo, m.ne, t, G);
-  int64_t base[4];
-  double u[4][3], hu[4][3], du[4][3], dhu[4][3], pr[4], dp[4];
-#pragma unroll
-  for (int A = 0; A < 4; ++A) {
-    const int64_t a = m.tets[A * m.ne + t];
-    base[A] = a * NCH * N + s;
-    const double* q = Sy + base[A];
-    const double* d = Sv + base[A];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      u[A][i] = q[i * N];
-      hu[A][i] = q[(4 + i) * N];
-      du[A][i] = d[i * N];
-      dhu[A][i] = d[(4 + i) * N];
-    }
-    pr[A] = q[3 * N];
-    dp[A] = d[3 * N];
-  }
-  double Gm[3][3], dG[3][3], gp[3], dgp[3], us[3], hs[3], dus[3], dhs[3];
+  double gA[3];
+  pick_grad(G, A, gA);
+  const int64_t base = (int64_t)m.tets[A * m.ne + t] * NCH * N + s;
+  const double* q = Sy + base;
+  const double* d = Sv + base;
+  double u[3], hu[3], du[3], dhu[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    gp[i] = dgp[i] = 0.0;
-    us[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
-    hs[i] = hu[0][i] + hu[1][i] + hu[2][i] + hu[3][i];
-    dus[i] = du[0][i] + du[1][i] + du[2][i] + du[3][i];
-    dhs[i] = dhu[0][i] + dhu[1][i] + dhu[2][i] + dhu[3][i];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) Gm[i][j] = dG[i][j] = 0.0;
+    u[i] = q[i * N];
+    hu[i] = q[(4 + i) * N];
+    du[i] = d[i * N];
+    dhu[i] = d[(4 + i) * N];
   }
+  const double pr = q[3 * N], dp = d[3 * N];
+  double Gm[3][3], dG[3][3], gp[3], dgp[3], uq[3], hq[3], duq[3], dhq[3], dus[3];
 #pragma unroll
-  for (int A = 0; A < 4; ++A)
+  for (int i = 0; i < 3; ++i) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      gp[i] += pr[A] * G.g[A][i];
-      dgp[i] += dp[A] * G.g[A][i];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        Gm[i][j] += u[A][i] * G.g[A][j];
-        dG[i][j] += du[A][i] * G.g[A][j];
-      }
+    for (int j = 0; j < 3; ++j) {
+      Gm[i][j] = quad_sum(u[i] * gA[j]);
+      dG[i][j] = quad_sum(du[i] * gA[j]);
     }
-  const double ddiv = dG[0][0] + dG[1][1] + dG[2][2];
-  const double dpbar = 0.25 * (dp[0] + dp[1] + dp[2] + dp[3]);
+    gp[i] = quad_sum(pr * gA[i]);
+    dgp[i] = quad_sum(dp * gA[i]);
+    dus[i] = quad_sum(du[i]);
+    uq[i] = QB * quad_sum(u[i]) + (QA - QB) * u[i];
+    hq[i] = QB * quad_sum(hu[i]) + (QA - QB) * hu[i];
+    duq[i] = QB * dus[i] + (QA - QB) * du[i];
+    dhq[i] = QB * quad_sum(dhu[i]) + (QA - QB) * dhu[i];
+  }
+  const double dpbar = 0.25 * quad_sum(dp);
   const double rho = p.rho;
-  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
   const double w = 0.25 * G.V;
-  double rm[4][3], rc[4], z[4][3], dS[3] = {0, 0, 0};
+  double adv[3], dadv[3], xu[3];
 #pragma unroll
-  for (int A = 0; A < 4; ++A) {
-    rc[A] = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) rm[A][i] = z[A][i] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
+    dadv[i] = duq[0] * Gm[i][0] + duq[1] * Gm[i][1] + duq[2] * Gm[i][2]
+            + uq[0] * dG[i][0] + uq[1] * dG[i][1] + uq[2] * dG[i][2];
   }
+  xi_mul(G, uq, xu);
+  const double tau =
+      1.0 / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + p.C_I * p.nu * p.nu * G.xixi);
+  const double dtau = -tau * tau * tau * (xu[0] * duq[0] + xu[1] * duq[1] + xu[2] * duq[2]);
+  double sv[3], ds[3], dgal[3];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double uq[3], hq[3], duq[3], dhq[3], adv[3], dadv[3], xu[3], L[3], dL[3], sv[3], ds[3],
-        dgal[3], c[4], dc[4];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      uq[i] = QB * us[i] + (QA - QB) * u[q][i];
-      hq[i] = QB * hs[i] + (QA - QB) * hu[q][i];
-      duq[i] = QB * dus[i] + (QA - QB) * du[q][i];
-      dhq[i] = QB * dhs[i] + (QA - QB) * dhu[q][i];
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
-      dadv[i] = duq[0] * Gm[i][0] + duq[1] * Gm[i][1] + duq[2] * Gm[i][2]
-              + uq[0] * dG[i][0] + uq[1] * dG[i][1] + uq[2] * dG[i][2];
-    }
-    xi_mul(G, uq, xu);
-    const double kap = uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + kap0;
-    const double tau = 1.0 / sqrt(kap);
-    const double dtau = -tau * tau * tau * (xu[0] * duq[0] + xu[1] * duq[1] + xu[2] * duq[2]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      L[i] = rho * (hq[i] + adv[i]) + gp[i];
-      dgal[i] = rho * (dhq[i] + dadv[i]);
-      dL[i] = dgal[i] + dgp[i];
-      sv[i] = tau * L[i];
-      ds[i] = dtau * L[i] + tau * dL[i];
-      dS[i] += w * ds[i];
-    }
-#pragma unroll
-    for (int A = 0; A < 4; ++A) {
-      c[A] = uq[0] * G.g[A][0] + uq[1] * G.g[A][1] + uq[2] * G.g[A][2];
-      dc[A] = duq[0] * G.g[A][0] + duq[1] * G.g[A][1] + duq[2] * G.g[A][2];
-    }
-#pragma unroll
-    for (int A = 0; A < 4; ++A) {
-      const double NA = (A == q) ? QA : QB;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        rm[A][i] += w * (NA * dgal[i] + dc[A] * sv[i] + c[A] * ds[i]);
-        z[A][i] += w * NA * ds[i];
-      }
-    }
+  for (int i = 0; i < 3; ++i) {
+    const double L = rho * (hq[i] + adv[i]) + gp[i];
+    dgal[i] = rho * (dhq[i] + dadv[i]);
+    sv[i] = tau * L;
+    ds[i] = dtau * L + tau * (dgal[i] + dgp[i]);
   }
+  double cr[4][NCH];
+#pragma unroll
+  for (int B = 0; B < 4; ++B) {
+    const double NB = (B == A) ? QA : QB;
+    const double c = uq[0] * G.g[B][0] + uq[1] * G.g[B][1] + uq[2] * G.g[B][2];
+    const double dc = duq[0] * G.g[B][0] + duq[1] * G.g[B][1] + duq[2] * G.g[B][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cr[B][i] = w * (NB * dgal[i] + dc * sv[i] + c * ds[i]);
+      cr[B][4 + i] = w * NB * ds[i];
+    }
+    cr[B][3] = w * (G.g[B][0] * ds[0] + G.g[B][1] * ds[1] + G.g[B][2] * ds[2]) / rho;
+  }
+  quad_reduce_scatter(A, cr, res);
   const double V = G.V;
   const double ms = p.shift * V * (1.0 / 20.0);
 #pragma unroll
-  for (int A = 0; A < 4; ++A) {
+  for (int i = 0; i < 3; ++i)
+    res[i] += V * (p.mu * (gA[0] * dG[i][0] + gA[1] * dG[i][1] + gA[2] * dG[i][2]) - gA[i] * dpbar)
+            + ms * (dus[i] + du[i]);
+  res[3] += w * (dG[0][0] + dG[1][1] + dG[2][2]);
+  return base;
+}
+
+// Element block of EB consecutive tetrahedra per workgroup: the lanes loop
+// over (element, sample, node) quads, add their node rows into an LDS
+// accumulator indexed by the block's unique nodes (precomputed on the host),
+// and the workgroup then adds each unique node's 7 x N block to the global
+// accumulator once (contiguous atomics), instead of one atomic per element
+// row.  Device-scope FP64 atomics are resolved beyond the per-XCD L2, so
+// their count is what this removes.
+template <int KIND>
+__global__ void __launch_bounds__(BLK)
+k_elem_block(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __restrict__ Sv,
+             double* __restrict__ acc, ElemBlocks eb, int64_t nlogical) {
+  extern __shared__ double sacc[];  // [U][NCH][N]
+  const int64_t b = xcd_block(nlogical);
+  if (b < 0) return;
+  const int N = p.N;
+  const int CN = NCH * N;
+  const int64_t e0 = b * eb.size;
+  const int nel = (int)min<int64_t>(eb.size, m.ne - e0);
+  const int32_t p0 = eb.ptr[b];
+  const int U = eb.ptr[b + 1] - p0;
+  for (int i = threadIdx.x; i < U * CN; i += BLK) sacc[i] = 0.0;
+  __syncthreads();
+  const int total = nel * N * 4;
+  for (int it = threadIdx.x; it < total; it += BLK) {  // quads stay aligned (BLK % 4 == 0)
+    const int A = it & 3;
+    const int ts = it >> 2;
+    const int el = ts / N;
+    const int s = ts - el * N;
+    const int64_t t = e0 + el;
+    double r[NCH];
+    if (KIND == 0)
+      residual_lane(m, p, Sy, t, s, A, r);
+    else
+      jvp_exact_lane(m, p, Sy, Sv, t, s, A, r);
+    double* dst = sacc + eb.slot[A * m.ne + t] * CN + s;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-      rm[A][i] += V * (p.mu * (G.g[A][0] * dG[i][0] + G.g[A][1] * dG[i][1] + G.g[A][2] * dG[i][2])
-                       - G.g[A][i] * dpbar)
-                + ms * (dus[i] + du[A][i]);
-    rc[A] = w * ddiv + (G.g[A][0] * dS[0] + G.g[A][1] * dS[1] + G.g[A][2] * dS[2]) / rho;
+    for (int c = 0; c < NCH; ++c)
+      __hip_atomic_fetch_add(dst + c * N, r[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  scatter_rows(acc, base, N, rm, rc, z, true);
+  __syncthreads();
+  for (int i = threadIdx.x; i < U * CN; i += BLK) {
+    const int u = i / CN;
+    const int r = i - u * CN;
+    atomic_add(acc + (int64_t)eb.nodes[p0 + u] * CN + r, sacc[i]);
+  }
 }
 
 // The paper's tangent C + P (eqs. K_mat, ctangent) applied matrix-free:
@@ -1088,17 +1096,20 @@ hipError_t outlet_flux(const DevMesh& m, int N, const double* S, double* Q, hipS
 }
 
 hipError_t elem_residual(const DevMesh& m, const Phys& p, const double* S, double* acc,
-                         hipStream_t st) {
-  const int64_t nb = (m.ne * p.N + BLK - 1) / BLK;
-  hipLaunchKernelGGL(k_elem_residual, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, S, acc, nb);
+                         const ElemBlocks& eb, hipStream_t st) {
+  const int64_t nb = (m.ne + eb.size - 1) / eb.size;
+  const size_t lds = sizeof(double) * (size_t)eb.max_unique * NCH * p.N;
+  hipLaunchKernelGGL(k_elem_block<0>, dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, S, S, acc, eb,
+                     nb);
   return hipGetLastError();
 }
 
 hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
-                          double* acc, hipStream_t st) {
-  const int64_t nb = (m.ne * p.N + BLK - 1) / BLK;
-  hipLaunchKernelGGL(k_elem_jvp_exact, dim3(xcd_grid(nb)), dim3(BLK), 0, st, m, p, Sy, Sv, acc,
-                     nb);
+                          double* acc, const ElemBlocks& eb, hipStream_t st) {
+  const int64_t nb = (m.ne + eb.size - 1) / eb.size;
+  const size_t lds = sizeof(double) * (size_t)eb.max_unique * NCH * p.N;
+  hipLaunchKernelGGL(k_elem_block<1>, dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, Sy, Sv, acc,
+                     eb, nb);
   return hipGetLastError();
 }
 
