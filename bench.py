@@ -86,7 +86,7 @@ def cpu_baseline(P, Y, V, budget_s=30.0):
                       f"{dt:.1f} s), scaled by element count"}
 
 
-def womersley_time_to_solution(hbl, torch, log):
+def womersley_time_to_solution(hbl, torch, log, precision="fp64"):
     """Complete FP64 solve of the Womersley-pipe workload to 1e-8 from its
     plain start (K = 0 solve broadcast), after one untimed warm-up solve."""
     from dataclasses import replace
@@ -109,11 +109,12 @@ def womersley_time_to_solution(hbl, torch, log):
         Y = torch.zeros((4, N, n), dtype=torch.float64, device="cuda:0")
         Y[:, 0] = Ys[:, 0]
         t = time.time()
-        r = hbl.newton_solve(gm, prm, bc, Y, hbl.SolveOptions(rtol=1e-8, max_newton=300,
-                                                             max_gmres=500),
-                             raise_on_noconv=False)
+        r = hbl.newton_solve(gm, prm, bc, Y, hbl.SolveOptions(
+            rtol=1e-8, max_newton=300, max_gmres=500,
+            precision=hbl.HB_MIXED if precision == "mixed" else hbl.HB_F64),
+            raise_on_noconv=False)
         t_solve = time.time() - t
-        res = {"workload": "womersley_pipe", "n_nodes": n, "K": prm.K,
+        res = {"workload": "womersley_pipe", "precision": precision, "n_nodes": n, "K": prm.K,
                "seconds": t_solve, "plain_start_seconds": t_plain,
                "total_seconds": t_solve + t_plain, "newton_iters": r["newton_iters"],
                "gmres_iters": r["gmres_iters"], "status": r["status"],
@@ -138,6 +139,8 @@ def main():
     ap.add_argument("--plain-newton", type=int, default=30)
     ap.add_argument("--max-gmres", type=int, default=300)
     ap.add_argument("--cfl-max", type=float, default=0.0)
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--no-time-to-solution", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
@@ -206,6 +209,22 @@ def main():
             stages[k] += tt[k] / args.jv_reps
         e1.synchronize()
         tot += e0.elapsed_time(e1) / args.jv_reps
+    V32 = V.float()
+    JV32 = torch.empty_like(V32)
+    for _ in range(5):
+        hbl.jvp(gm, prm, bc, Y0, V32, JV32)
+    torch.cuda.synchronize()
+    stages32 = {k: 0.0 for k in hbl.Mesh.STAGES}
+    tot32 = 0.0
+    for _ in range(args.jv_reps):
+        e0.record(st)
+        hbl.jvp(gm, prm, bc, Y0, V32, JV32)
+        e1.record(st)
+        tt = gm.last_timings()
+        for k in stages32:
+            stages32[k] += tt[k] / args.jv_reps
+        e1.synchronize()
+        tot32 += e0.elapsed_time(e1) / args.jv_reps
     gm.set_timing(False)
     dofs = 4 * n * N
     jv_public = dofs / (tot * 1e-3) / 1e9
@@ -230,31 +249,47 @@ def main():
         out.update({"value": jv_public, "steps": args.jv_reps, "warmup": 5, "ms_per_step": tot,
                     "step": "one public hb_jvp call"})
     else:
-        opts = hbl.SolveOptions(rtol=1e-30, max_newton=1, max_gmres=args.max_gmres,
-                                cfl_max=args.cfl_max, verbose=int(args.verbose))
-        Y = Y0.clone()
-        for _ in range(args.warmup):
-            hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False)
-        torch.cuda.synchronize()
-        reps = []
-        t = time.time()
-        for _ in range(args.steps):
-            reps.append(hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False))
-        torch.cuda.synchronize()
-        wall = (time.time() - t) / args.steps
-        n_jv = sum(r["n_jv"] for r in reps)
-        jv_ms = sum(r["jv_ms"] for r in reps)
-        out.update({"value": dofs * n_jv / (jv_ms * 1e-3) / 1e9, "steps": args.steps,
-                    "warmup": args.warmup, "ms_per_step": wall * 1e3,
-                    "step": "one FP64 inexact Newton step (residual, preconditioner, GMRES "
-                            "eta=0.03 with exact Jv, update) on the T-junction",
+        def newton_steps(precision):
+            opts = hbl.SolveOptions(rtol=1e-30, max_newton=1, max_gmres=args.max_gmres,
+                                    cfl_max=args.cfl_max, verbose=int(args.verbose),
+                                    precision=precision)
+            Y = Y0.clone()
+            for _ in range(args.warmup):
+                hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            reps = []
+            t = time.time()
+            for _ in range(args.steps):
+                reps.append(hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False))
+            torch.cuda.synchronize()
+            wall = (time.time() - t) / args.steps
+            n_jv = sum(r["n_jv"] for r in reps)
+            jv_ms = sum(r["jv_ms"] for r in reps)
+            return {"jv_gdofs": dofs * n_jv / (jv_ms * 1e-3) / 1e9, "ms_per_step": wall * 1e3,
                     "gmres_iters_per_step": [r["gmres_iters"] for r in reps],
                     "residual_per_step": [r["r_final"] for r in reps],
-                    "plain_start_s": plain_s,
-                    "jv_ms_avg": jv_ms / max(n_jv, 1)})
-        out["time_to_1e8"] = womersley_time_to_solution(hbl, torch, log)
+                    "jv_ms_avg": jv_ms / max(n_jv, 1)}
+        main_prec = "mixed" if args.precision == "mixed" else "fp64"
+        res = {p_: newton_steps(hbl.HB_MIXED if p_ == "mixed" else hbl.HB_F64)
+               for p_ in (["fp64", "mixed"] if args.precision == "both" else [main_prec])}
+        r0 = res[main_prec]
+        out.update({"value": r0["jv_gdofs"], "steps": args.steps, "warmup": args.warmup,
+                    "ms_per_step": r0["ms_per_step"],
+                    "step": f"one {main_prec.upper()} inexact Newton step (residual, "
+                            "preconditioner, GMRES eta=0.03 with exact Jv, update) on the "
+                            "T-junction",
+                    "gmres_iters_per_step": r0["gmres_iters_per_step"],
+                    "residual_per_step": r0["residual_per_step"],
+                    "plain_start_s": plain_s, "jv_ms_avg": r0["jv_ms_avg"]})
+        if "mixed" in res and main_prec != "mixed":
+            out["mixed"] = res["mixed"]
+        if not args.no_time_to_solution:
+            out["time_to_1e8"] = {p_: womersley_time_to_solution(hbl, torch, log, p_)
+                                  for p_ in res}
     out["jv_public"] = {"value": jv_public, "unit": "GDOF-modes/s", "ms": tot,
                         "stages_ms": stages}
+    out["jv_public_fp32"] = {"value": dofs / (tot32 * 1e-3) / 1e9, "unit": "GDOF-modes/s",
+                             "ms": tot32, "stages_ms": stages32}
     out["roofline"] = roofline
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, Y0.cpu().numpy(), V.cpu().numpy())

@@ -148,8 +148,15 @@ int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const 
  * diag_n(K_AA) + rho int N_A^2 H plus the stabilisation's time terms
  * diag(X) H - H diag(X) - rho H diag(T) H with T = int tau N_A^2 and
  * X = int rho tau (u.grad N_A) N_A, inverted exactly per node; the pressure
- * rows keep 1 / L_AA.  Both change iteration counts, not the root. */
+ * rows keep 1 / L_AA (requires K <= 31).  Both change iteration counts, not
+ * the root. */
 enum { HB_PREC_JACOBI = 0, HB_PREC_NODE_TIME = 1 };
+
+/* hb_solve_opts.precision: HB_F64 (= 0), or HB_MIXED: FP32 Krylov basis and
+ * FP32 Jacobian-vector products (on an FP32 copy of the state) inside GMRES,
+ * with the FP64 residual, FP64 Gram-Schmidt coefficients and FP64 Newton
+ * update as the outer (iterative refinement) loop. */
+enum { HB_MIXED = 1 };
 
 typedef struct {
   double rtol;       /* stop when ||r||_2 <= rtol * r_ref (default 1e-8)              */
@@ -160,7 +167,7 @@ typedef struct {
   int32_t restart;   /* GMRES restart length (default 50)                             */
   int32_t max_newton;
   int32_t max_gmres; /* per Newton step                                               */
-  int32_t precision; /* HB_F64, or 1 = mixed (FP32 Jv and Krylov basis)               */
+  int32_t precision; /* HB_F64 or HB_MIXED                                           */
   int32_t jv_kind;   /* HB_JV_EXACT or HB_JV_PAPER for the Krylov operator            */
   int32_t verbose;   /* print one line per Newton step to stderr                      */
   int32_t precond;   /* HB_PREC_JACOBI (the paper's diag(P)) or HB_PREC_NODE_TIME    */

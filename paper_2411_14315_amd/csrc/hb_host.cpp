@@ -11,6 +11,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "hb.h"
@@ -28,12 +29,12 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-#define HB_CHECK(expr)                                                              \
+#define HB_CHECK(...)                                                               \
   do {                                                                              \
-    hipError_t e_ = (expr);                                                         \
+    hipError_t e_ = (__VA_ARGS__);                                                  \
     if (e_ != hipSuccess)                                                           \
       return fail(e_ == hipErrorOutOfMemory ? HB_ERR_OOM : HB_ERR_DEVICE,           \
-                  std::string(#expr) + ": " + hipGetErrorString(e_));               \
+                  std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));        \
   } while (0)
 
 struct DevBuf {
@@ -60,6 +61,7 @@ struct DevBuf {
 struct Workspace {
   int N = -1;
   DevBuf Sy, Sv, acc, tab, small, dg, dinv, binv;
+  DevBuf Sy32, Sv32, acc32;  // FP32 state copy, direction and accumulator (mixed precision)
   std::vector<double> tab_host;
   std::vector<double> bc_host;  // hs (n_out N) then R (n_out), as last uploaded
   bool bc_has_R = false;
@@ -93,7 +95,7 @@ struct hb_mesh {
   size_t bytes_held() const {
     return tets.bytes + geo.bytes + dmask.bytes + of.bytes + ofn.bytes + oid.bytes + ws.Sy.bytes +
            ws.Sv.bytes + ws.acc.bytes + ws.tab.bytes + ws.small.bytes + ws.dg.bytes +
-           ws.dinv.bytes + ws.binv.bytes + mass.bytes + bmaps[0].ptr.bytes + bmaps[0].nodes.bytes +
+           ws.dinv.bytes + ws.binv.bytes + ws.Sy32.bytes + ws.Sv32.bytes + ws.acc32.bytes + mass.bytes + bmaps[0].ptr.bytes + bmaps[0].nodes.bytes +
            bmaps[0].slot.bytes + bmaps[1].ptr.bytes + bmaps[1].nodes.bytes + bmaps[1].slot.bytes +
            bmaps[2].ptr.bytes + bmaps[2].nodes.bytes + bmaps[2].slot.bytes + bmaps[3].ptr.bytes +
            bmaps[3].nodes.bytes + bmaps[3].slot.bytes;
@@ -249,11 +251,23 @@ Ptrs small_ptrs(hb_mesh* m) {
   return p;
 }
 
-// Largest element block whose LDS accumulator (unique nodes x 7 x N
-// doubles) stays within 64 KiB, so that two or more workgroups fit per CU.
-const hb::ElemBlocks& pick_blocks(const hb_mesh* m, int N) {
+int ensure_f32(hb_mesh* m) {
+  Workspace& w = m->ws;
+  const size_t b = sizeof(float) * (size_t)m->dm.n * hb::NCH * w.N;
+  HB_CHECK(w.Sy32.ensure(b));
+  HB_CHECK(w.Sv32.ensure(b));
+  HB_CHECK(w.acc32.ensure(b));
+  return HB_OK;
+}
+
+#ifndef HB_LDS_BUDGET
+#define HB_LDS_BUDGET (64 * 1024)
+#endif
+// Largest element block whose LDS accumulator (unique nodes x 7 x N values
+// of `elem` bytes) stays within the LDS budget per workgroup.
+const hb::ElemBlocks& pick_blocks(const hb_mesh* m, int N, size_t elem = sizeof(double)) {
   for (const auto& b : m->bmaps)
-    if ((size_t)b.eb.max_unique * hb::NCH * N * sizeof(double) <= 64 * 1024) return b.eb;
+    if ((size_t)b.eb.max_unique * hb::NCH * N * elem <= HB_LDS_BUDGET) return b.eb;
   return m->bmaps[3].eb;
 }
 
@@ -567,18 +581,18 @@ int hb_residual(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, cons
   Ptrs s = small_ptrs(m);
   const double* tab = w.tab.as<double>();
   HB_CHECK(mark(m, 0, st));
-  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(),
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(),
                                 w.acc.as<double>(), s.Q, m->dm.n_out * N, st));
   HB_CHECK(mark(m, 1, st));
   HB_CHECK(mark(m, 2, st));
-  if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, w.Sy.as<double>(), s.Q, st));
+  if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, w.Sy.as<double>(), s.Q, st));
   HB_CHECK(mark(m, 3, st));
   HB_CHECK(hb::elem_residual(m->dm, p, w.Sy.as<double>(), w.acc.as<double>(),
                              pick_blocks(m, N), st));
   HB_CHECK(mark(m, 4, st));
   HB_CHECK(hb::face_residual(m->dm, p, w.Sy.as<double>(), s.hs, s.R, s.Q, w.acc.as<double>(), st));
   HB_CHECK(mark(m, 5, st));
-  HB_CHECK(hb::samples_to_modal(m->dm, N, w.acc.as<double>(), 1, 1, hb::NCH, tab, R, st));
+  HB_CHECK(hb::samples_to_modal<double, double>(m->dm, N, w.acc.as<double>(), 1, 1, hb::NCH, tab, R, st));
   HB_CHECK(mark(m, 6, st));
   return HB_OK;
 }
@@ -587,8 +601,9 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
            const void* V, void* JV, int32_t flags, void* stream) {
   if (!mesh || !Y || !V || !JV) return fail(HB_ERR_ARG, "NULL argument");
   if (flags & ~3) return fail(HB_ERR_ARG, "unknown flags");
-  if (flags & HB_F32) return fail(HB_ERR_ARG, "HB_F32 vectors are not supported by hb_jvp");
   const int kind = flags & 1;
+  if ((flags & HB_F32) && kind != HB_JV_EXACT)
+    return fail(HB_ERR_ARG, "HB_F32 is available for HB_JV_EXACT only");
   hb_mesh* m = const_cast<hb_mesh*>(mesh);
   hipStream_t st = (hipStream_t)stream;
   int rc = prepare(m, prm, bc, st);
@@ -601,22 +616,47 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
   double* Sy = w.Sy.as<double>();
   double* Sv = w.Sv.as<double>();
   double* acc = w.acc.as<double>();
+  if (flags & HB_F32) {
+    rc = ensure_f32(m);
+    if (rc) return rc;
+    float* Sy32 = w.Sy32.as<float>();
+    float* Sv32 = w.Sv32.as<float>();
+    float* acc32 = w.acc32.as<float>();
+    HB_CHECK(mark(m, 0, st));
+    HB_CHECK(hb::modal_to_samples<double, float>(m->dm, N, Y, bc->dirichlet, 0, tab, Sy32,
+                                                 nullptr, nullptr, 0, st));
+    HB_CHECK(mark(m, 1, st));
+    HB_CHECK(hb::modal_to_samples<float, float>(m->dm, N, (const float*)V, bc->dirichlet, 1, tab,
+                                                Sv32, acc32, s.dQ, m->dm.n_out * N, st));
+    HB_CHECK(mark(m, 2, st));
+    if (s.R) HB_CHECK(hb::outlet_flux<float>(m->dm, N, Sv32, s.dQ, st));
+    HB_CHECK(mark(m, 3, st));
+    HB_CHECK(hb::elem_jvp_exact<float>(m->dm, p, Sy32, Sv32, acc32,
+                                       pick_blocks(m, N, sizeof(float)), st));
+    HB_CHECK(mark(m, 4, st));
+    HB_CHECK(hb::face_jvp<float>(m->dm, p, Sy32, Sv32, s.R, s.dQ, acc32, st));
+    HB_CHECK(mark(m, 5, st));
+    HB_CHECK(hb::samples_to_modal<float, float>(m->dm, N, acc32, 1, 1, hb::NCH, tab, (float*)JV,
+                                                st));
+    HB_CHECK(mark(m, 6, st));
+    return HB_OK;
+  }
   HB_CHECK(mark(m, 0, st));
-  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, Sy, nullptr, nullptr, 0, st));
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab, Sy, nullptr, nullptr, 0, st));
   HB_CHECK(mark(m, 1, st));
-  HB_CHECK(hb::modal_to_samples(m->dm, N, (const double*)V, bc->dirichlet, 1, tab, Sv, acc, s.dQ,
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, (const double*)V, bc->dirichlet, 1, tab, Sv, acc, s.dQ,
                                 m->dm.n_out * N, st));
   HB_CHECK(mark(m, 2, st));
-  if (kind == HB_JV_EXACT && s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
+  if (kind == HB_JV_EXACT && s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, Sv, s.dQ, st));
   HB_CHECK(mark(m, 3, st));
   if (kind == HB_JV_EXACT)
-    HB_CHECK(hb::elem_jvp_exact(m->dm, p, Sy, Sv, acc, pick_blocks(m, N), st));
+    HB_CHECK(hb::elem_jvp_exact<double>(m->dm, p, Sy, Sv, acc, pick_blocks(m, N), st));
   else
     HB_CHECK(hb::elem_jvp_paper(m->dm, p, Sy, Sv, acc, st));
   HB_CHECK(mark(m, 4, st));
-  if (kind == HB_JV_EXACT) HB_CHECK(hb::face_jvp(m->dm, p, Sy, Sv, s.R, s.dQ, acc, st));
+  if (kind == HB_JV_EXACT) HB_CHECK(hb::face_jvp<double>(m->dm, p, Sy, Sv, s.R, s.dQ, acc, st));
   HB_CHECK(mark(m, 5, st));
-  HB_CHECK(hb::samples_to_modal(m->dm, N, acc, kind == HB_JV_EXACT, 1, hb::NCH, tab, (double*)JV,
+  HB_CHECK(hb::samples_to_modal<double, double>(m->dm, N, acc, kind == HB_JV_EXACT, 1, hb::NCH, tab, (double*)JV,
                                 st));
   HB_CHECK(mark(m, 6, st));
   return HB_OK;
@@ -634,18 +674,27 @@ int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const 
   const int N = w.N;
   const Phys p = make_phys(prm, shift);
   const double* tab = w.tab.as<double>();
-  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(), nullptr,
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(), nullptr,
                                 nullptr, 0, st));
-  HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * 2 * N, st));
+  HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), m->dm.n * 2 * N, st));
   HB_CHECK(hb::elem_jacobi(m->dm, p, w.Sy.as<double>(), w.dg.as<double>(), 0, st));
   HB_CHECK(hb::jacobi_out(m->dm, N, 2, w.dg.as<double>(), D, nullptr, st));
   return HB_OK;
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------ the solver
 
 namespace {
 
+// Inexact Newton-GMRES in time-sample space.  T is the Krylov type: double
+// for the FP64 solve; float for the mixed-precision solve, where the basis
+// vectors, the Jacobian-vector products (on an FP32 copy of the state) and
+// the GMRES solution are FP32 while the residual, the preconditioner, the
+// Gram-Schmidt coefficients (FP64 accumulation) and the Newton update stay
+// FP64, so that the outer iteration refines to the FP64 residual.
+template <typename T>
 struct Solver {
   hb_mesh* m;
   const hb_params* prm;
@@ -667,7 +716,44 @@ struct Solver {
     if (ev1) (void)hipEventDestroy(ev1);
   }
 
-  double* Q(int j) { return basis.as<double>() + (size_t)j * L; }
+  T* Q(int j) { return basis.as<T>() + (size_t)j * L; }
+  // the state as seen by the Krylov operator
+  const T* state() {
+    if constexpr (std::is_same<T, double>::value) return m->ws.Sy.as<double>();
+    else return m->ws.Sy32.as<float>();
+  }
+  T* dir() {
+    if constexpr (std::is_same<T, double>::value) return m->ws.Sv.as<double>();
+    else return m->ws.Sv32.as<float>();
+  }
+  T* accum() {
+    if constexpr (std::is_same<T, double>::value) return m->ws.acc.as<double>();
+    else return m->ws.acc32.as<float>();
+  }
+
+  int alloc() {
+    HB_CHECK(basis.ensure(sizeof(T) * (size_t)(restart + 1) * L));
+    HB_CHECK(xvec.ensure(sizeof(T) * L));
+    HB_CHECK(rvec.ensure(sizeof(T) * L));
+    HB_CHECK(tmp.ensure(sizeof(T) * L));
+    HB_CHECK(partial.ensure(sizeof(double) * (size_t)(restart + 2) * nblk));
+    HB_CHECK(hdev.ensure(sizeof(double) * (4 * (size_t)(restart + 1) + 8)));
+    HB_CHECK(hipEventCreate(&ev0));
+    HB_CHECK(hipEventCreate(&ev1));
+    if constexpr (!std::is_same<T, double>::value) {
+      int rc = ensure_f32(m);
+      if (rc) return rc;
+    }
+    return HB_OK;
+  }
+
+  // FP32 copy of the state (mixed precision), after every state change.
+  int sync_state() {
+    if constexpr (!std::is_same<T, double>::value)
+      HB_CHECK(hb::vec_copy_scaled<float, double>(m->ws.Sy32.as<float>(), m->ws.Sy.as<double>(),
+                                                  m->dm.n * hb::NCH * N, 1.0, st));
+    return HB_OK;
+  }
 
   int residual(double* r, double& nrm) {
     Workspace& w = m->ws;
@@ -675,18 +761,22 @@ struct Solver {
     const double* tab = w.tab.as<double>();
     const Phys p = make_phys(prm, 0.0);
     double* Sy = w.Sy.as<double>();
-    HB_CHECK(hb::prepare_direction(m->dm, N, Sy, hb::NCH, nullptr, nullptr, 0, tab, Sy,
-                                   w.acc.as<double>(),
-                                   s.Q, m->dm.n_out * N, st));
-    if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sy, s.Q, st));
+    HB_CHECK(hb::prepare_direction<double, double>(m->dm, N, Sy, hb::NCH, nullptr, nullptr, 0,
+                                                   tab, Sy, w.acc.as<double>(), s.Q,
+                                                   m->dm.n_out * N, st));
+    if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, Sy, s.Q, st));
     HB_CHECK(hb::elem_residual(m->dm, p, Sy, w.acc.as<double>(), pick_blocks(m, N), st));
     HB_CHECK(hb::face_residual(m->dm, p, Sy, s.hs, s.R, s.Q, w.acc.as<double>(), st));
-    HB_CHECK(hb::finish_rows(m->dm, N, w.acc.as<double>(), 1, tab, nullptr, r, st));
-    return norm(r, nrm);
+    HB_CHECK(hb::finish_rows<double, double>(m->dm, N, w.acc.as<double>(), 1, tab, nullptr, r,
+                                             st));
+    int rc = sync_state();
+    if (rc) return rc;
+    return norm<double>(r, nrm);
   }
 
-  int norm(const double* x, double& out) {
-    HB_CHECK(hb::vec_dots(x, L, 1, x, L, partial.as<double>(), nblk, hdev.as<double>(), st));
+  template <typename V>
+  int norm(const V* x, double& out) {
+    HB_CHECK(hb::vec_dots<V>(x, L, 1, x, L, partial.as<double>(), nblk, hdev.as<double>(), st));
     double v = 0.0;
     HB_CHECK(hipMemcpyAsync(&v, hdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
     HB_CHECK(hipStreamSynchronize(st));
@@ -695,24 +785,29 @@ struct Solver {
   }
 
   // w = J M^-1 q (+ shift mass), Dirichlet momentum rows = q.
-  int apply(const double* q, double* wout, double shift) {
+  int apply(const T* q, T* wout, double shift) {
     Workspace& w = m->ws;
     Ptrs s = small_ptrs(m);
     const double* tab = w.tab.as<double>();
     const Phys p = make_phys(prm, shift);
-    double* Sv = w.Sv.as<double>();
-    double* acc = w.acc.as<double>();
+    T* Sv = dir();
+    T* acc = accum();
     HB_CHECK(hipEventRecord(ev0, st));
-    HB_CHECK(hb::prepare_direction(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab, Sv, acc,
-                                   s.dQ, m->dm.n_out * N, st));
+    HB_CHECK(hb::prepare_direction<T, T>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab, Sv,
+                                         acc, s.dQ, m->dm.n_out * N, st));
     if (jv_kind == HB_JV_EXACT) {
-      if (s.R) HB_CHECK(hb::outlet_flux(m->dm, N, Sv, s.dQ, st));
-      HB_CHECK(hb::elem_jvp_exact(m->dm, p, w.Sy.as<double>(), Sv, acc, pick_blocks(m, N), st));
-      HB_CHECK(hb::face_jvp(m->dm, p, w.Sy.as<double>(), Sv, s.R, s.dQ, acc, st));
-      HB_CHECK(hb::finish_rows(m->dm, N, acc, 1, tab, q, wout, st));
+      if (s.R) HB_CHECK(hb::outlet_flux<T>(m->dm, N, Sv, s.dQ, st));
+      HB_CHECK(hb::elem_jvp_exact<T>(m->dm, p, state(), Sv, acc, pick_blocks(m, N, sizeof(T)),
+                                     st));
+      HB_CHECK(hb::face_jvp<T>(m->dm, p, state(), Sv, s.R, s.dQ, acc, st));
+      HB_CHECK(hb::finish_rows<T, T>(m->dm, N, acc, 1, tab, q, wout, st));
     } else {
-      HB_CHECK(hb::elem_jvp_paper(m->dm, p, w.Sy.as<double>(), Sv, acc, st));
-      HB_CHECK(hb::finish_rows(m->dm, N, acc, 0, tab, q, wout, st));
+      if constexpr (std::is_same<T, double>::value) {
+        HB_CHECK(hb::elem_jvp_paper(m->dm, p, w.Sy.as<double>(), Sv, acc, st));
+        HB_CHECK(hb::finish_rows<double, double>(m->dm, N, acc, 0, tab, q, wout, st));
+      } else {
+        return fail(HB_ERR_ARG, "the paper tangent is available in FP64 only");
+      }
     }
     HB_CHECK(hipEventRecord(ev1, st));
     HB_CHECK(hipEventSynchronize(ev1));
@@ -725,12 +820,12 @@ struct Solver {
 
   // Right-preconditioned restarted GMRES on (J M^-1) x = -r; CGS2.
   int gmres(const double* r, double shift, double eta, int max_it, int& iters) {
-    double* x = xvec.as<double>();
-    double* rl = rvec.as<double>();
-    HB_CHECK(hb::vec_zero(x, L, st));
-    HB_CHECK(hb::vec_copy_scaled(rl, r, L, -1.0, st));
+    T* x = xvec.as<T>();
+    T* rl = rvec.as<T>();
+    HB_CHECK(hb::vec_zero<T>(x, L, st));
+    HB_CHECK((hb::vec_copy_scaled<T, double>(rl, r, L, -1.0, st)));
     double beta;
-    int rc = norm(rl, beta);
+    int rc = norm<T>(rl, beta);
     if (rc) return rc;
     iters = 0;
     if (beta == 0.0) return HB_OK;
@@ -740,23 +835,23 @@ struct Solver {
     hhost.assign(2 * (mr + 1) + 1, 0.0);
     double bc = beta;
     while (true) {
-      HB_CHECK(hb::vec_copy_scaled(Q(0), rl, L, 1.0 / bc, st));
+      HB_CHECK((hb::vec_copy_scaled<T, T>(Q(0), rl, L, 1.0 / bc, st)));
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = bc;
       int jend = 0;
       bool done = false;
       for (int j = 0; j < mr; ++j) {
-        double* wj = Q(j + 1);
+        T* wj = Q(j + 1);
         rc = apply(Q(j), wj, shift);
         if (rc) return rc;
         double* h1 = hdev.as<double>();
         double* h2 = h1 + (mr + 1);
         double* h3 = h2 + (mr + 1);
-        HB_CHECK(hb::vec_dots(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h1, st));
-        HB_CHECK(hb::vec_axpy_multi(wj, Q(0), L, j + 1, h1, -1.0, L, st));
-        HB_CHECK(hb::vec_dots(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h2, st));
-        HB_CHECK(hb::vec_axpy_multi(wj, Q(0), L, j + 1, h2, -1.0, L, st));
-        HB_CHECK(hb::vec_dots(wj, L, 1, wj, L, partial.as<double>(), nblk, h3, st));
+        HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h1, st));
+        HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h1, -1.0, L, st));
+        HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h2, st));
+        HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h2, -1.0, L, st));
+        HB_CHECK(hb::vec_dots<T>(wj, L, 1, wj, L, partial.as<double>(), nblk, h3, st));
         HB_CHECK(hipMemcpyAsync(hhost.data(), h1, sizeof(double) * (2 * (mr + 1) + 1),
                                 hipMemcpyDeviceToHost, st));
         HB_CHECK(hipStreamSynchronize(st));
@@ -765,7 +860,7 @@ struct Solver {
         const double hn = std::sqrt(std::max(hhost[2 * (mr + 1)], 0.0));
         col[j + 1] = hn;
         if (!std::isfinite(hn)) return fail(HB_ERR_NAN, "non-finite Krylov vector");
-        if (hn > 0) HB_CHECK(hb::vec_scale(wj, L, nullptr, 1.0 / hn, st));
+        if (hn > 0) HB_CHECK(hb::vec_scale<T>(wj, L, 1.0 / hn, st));
         for (int k = 0; k < j; ++k) {
           const double a = col[k], b = col[k + 1];
           col[k] = cs[k] * a + sn[k] * b;
@@ -793,42 +888,46 @@ struct Solver {
       }
       double* ydev = hdev.as<double>() + 2 * (mr + 1) + 1;
       HB_CHECK(hipMemcpyAsync(ydev, yv.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
-      HB_CHECK(hb::vec_axpy_multi(x, Q(0), L, jend, ydev, 1.0, L, st));
+      HB_CHECK(hb::vec_axpy_multi<T>(x, Q(0), L, jend, ydev, 1.0, L, st));
       HB_CHECK(hipStreamSynchronize(st));
       if (done && (std::fabs(g[jend]) <= target || iters >= max_it)) break;
       // restart: rl = -r - (J M^-1) x
-      rc = apply(x, tmp.as<double>(), shift);
+      rc = apply(x, tmp.as<T>(), shift);
       if (rc) return rc;
-      HB_CHECK(hb::vec_copy_scaled(rl, r, L, -1.0, st));
+      HB_CHECK((hb::vec_copy_scaled<T, double>(rl, r, L, -1.0, st)));
       double one = 1.0;
       HB_CHECK(hipMemcpyAsync(ydev, &one, sizeof(double), hipMemcpyHostToDevice, st));
-      HB_CHECK(hb::vec_axpy_multi(rl, tmp.as<double>(), L, 1, ydev, -1.0, L, st));
-      rc = norm(rl, bc);
+      HB_CHECK(hb::vec_axpy_multi<T>(rl, tmp.as<T>(), L, 1, ydev, -1.0, L, st));
+      rc = norm<T>(rl, bc);
       if (rc) return rc;
       if (bc <= target || iters >= max_it) break;
     }
     return HB_OK;
   }
+
+  // state += M^-1 x (FP64), skipping Dirichlet velocity entries.
+  int update_state() {
+    Workspace& w = m->ws;
+    const double* tab = w.tab.as<double>();
+    if (binv) {
+      HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, xvec.as<T>(), 4, w.dinv.as<double>(),
+                                                 binv, 1, tab, w.Sv.as<double>(), nullptr,
+                                                 nullptr, 0, st)));
+      HB_CHECK(hb::vec_mul_dinv_add<double>(w.Sy.as<double>(), w.Sv.as<double>(), nullptr,
+                                            m->dm.dmask, m->dm.n, N, hb::NCH, hb::NCH, 1.0, st));
+    } else {
+      HB_CHECK(hb::vec_mul_dinv_add<T>(w.Sy.as<double>(), xvec.as<T>(), w.dinv.as<double>(),
+                                       m->dm.dmask, m->dm.n, N, hb::NCH, 4, 1.0, st));
+    }
+    return HB_OK;
+  }
 };
 
-}  // namespace
-
-int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
-                    const hb_solve_opts* opts, hb_solve_report* report, void* stream) {
-  if (!mesh || !Y || !opts || !report) return fail(HB_ERR_ARG, "NULL argument");
-  const auto t0 = std::chrono::steady_clock::now();
-  std::memset(report, 0, sizeof(*report));
-  report->status = HB_ERR_NOCONV;
-  if (opts->precision != HB_F64) return fail(HB_ERR_ARG, "only precision = HB_F64 is available");
-  if (opts->restart < 1 || opts->restart > 512) return fail(HB_ERR_ARG, "restart must be 1..512");
-  if (opts->max_newton < 0 || opts->max_gmres < 1) return fail(HB_ERR_ARG, "bad iteration limits");
-  if (!(opts->rtol > 0) || !(opts->gmres_eta > 0) || !(opts->cfl > 0) || !(opts->c1 >= 0))
-    return fail(HB_ERR_ARG, "rtol, gmres_eta, cfl must be positive");
-  hb_mesh* m = const_cast<hb_mesh*>(mesh);
-  hipStream_t st = (hipStream_t)stream;
-  int rc = prepare(m, prm, bc, st);
-  if (rc) return rc;
-  Solver S;
+template <typename T>
+int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
+               const hb_solve_opts* opts, hb_solve_report* report, hipStream_t st,
+               std::chrono::steady_clock::time_point t0) {
+  Solver<T> S;
   S.m = m;
   S.prm = prm;
   S.st = st;
@@ -839,24 +938,19 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
   S.jv_kind = opts->jv_kind == HB_JV_PAPER ? HB_JV_PAPER : HB_JV_EXACT;
   const int N = S.N;
   const int64_t L = S.L;
-  HB_CHECK(S.basis.ensure(sizeof(double) * (size_t)(S.restart + 1) * L));
-  HB_CHECK(S.xvec.ensure(sizeof(double) * L));
-  HB_CHECK(S.rvec.ensure(sizeof(double) * L));
-  HB_CHECK(S.tmp.ensure(sizeof(double) * L));
-  HB_CHECK(S.partial.ensure(sizeof(double) * (size_t)(S.restart + 2) * S.nblk));
-  HB_CHECK(S.hdev.ensure(sizeof(double) * (4 * (size_t)(S.restart + 1) + 8)));
+  int rc = S.alloc();
+  if (rc) return rc;
   if (opts->precond == HB_PREC_NODE_TIME) {
+    if (N > 64) return fail(HB_ERR_ARG, "HB_PREC_NODE_TIME needs K <= 31");
     HB_CHECK(m->ws.binv.ensure(sizeof(double) * (size_t)m->dm.n * N * N));
     S.binv = m->ws.binv.as<double>();
   } else if (opts->precond != HB_PREC_JACOBI) {
     return fail(HB_ERR_ARG, "unknown preconditioner");
   }
-  HB_CHECK(hipEventCreate(&S.ev0));
-  HB_CHECK(hipEventCreate(&S.ev1));
   Workspace& w = m->ws;
   const double* tab = w.tab.as<double>();
-  HB_CHECK(hb::modal_to_samples(m->dm, N, Y, bc->dirichlet, 0, tab, w.Sy.as<double>(), nullptr,
-                                nullptr, 0, st));
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab,
+                                                w.Sy.as<double>(), nullptr, nullptr, 0, st));
 
   // initial pseudo step: dt = cfl h_c / u_c (Section 2.3)
   const double hc = std::cbrt(6.0 * std::sqrt(2.0) * m->mean_vol);
@@ -907,7 +1001,7 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
     const double shift = opts->c1 * prm->rho / dt;
     const Phys pj = make_phys(prm, shift);
     const int nc = S.binv ? 4 : 2;
-    HB_CHECK(hb::vec_zero(w.dg.as<double>(), m->dm.n * nc * N, st));
+    HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), m->dm.n * nc * N, st));
     HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), S.binv ? 1 : 0, st));
     HB_CHECK(hb::jacobi_out(m->dm, N, nc, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
     if (S.binv)
@@ -917,15 +1011,8 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
     rc = S.gmres(r, shift, opts->gmres_eta, opts->max_gmres, gi);
     if (rc) return rc;
     report->gmres_iters += gi;
-    if (S.binv) {
-      HB_CHECK(hb::prepare_direction(m->dm, N, S.xvec.as<double>(), 4, w.dinv.as<double>(),
-                                     S.binv, 1, tab, w.Sv.as<double>(), nullptr, nullptr, 0, st));
-      HB_CHECK(hb::vec_mul_dinv_add(w.Sy.as<double>(), w.Sv.as<double>(), nullptr, m->dm.dmask,
-                                    m->dm.n, N, hb::NCH, hb::NCH, 1.0, st));
-    } else {
-      HB_CHECK(hb::vec_mul_dinv_add(w.Sy.as<double>(), S.xvec.as<double>(), w.dinv.as<double>(),
-                                    m->dm.dmask, m->dm.n, N, hb::NCH, 4, 1.0, st));
-    }
+    rc = S.update_state();
+    if (rc) return rc;
     double rn_new = 0.0;
     rc = S.residual(r, rn_new);
     if (rc) return rc;
@@ -940,7 +1027,8 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
   }
   report->newton_iters = it;
   report->r_final = rn;
-  HB_CHECK(hb::samples_to_modal(m->dm, N, w.Sy.as<double>(), 0, 0, hb::NCH, tab, Y, st));
+  HB_CHECK(hb::samples_to_modal<double, double>(m->dm, N, w.Sy.as<double>(), 0, 0, hb::NCH, tab,
+                                                Y, st));
   HB_CHECK(hipStreamSynchronize(st));
   report->status = status;
   report->jv_ms = S.jv_ms;
@@ -949,6 +1037,32 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (status != HB_OK) return fail(status, "Newton iteration limit reached");
   return HB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
+                    const hb_solve_opts* opts, hb_solve_report* report, void* stream) {
+  if (!mesh || !Y || !opts || !report) return fail(HB_ERR_ARG, "NULL argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  std::memset(report, 0, sizeof(*report));
+  report->status = HB_ERR_NOCONV;
+  if (opts->precision != HB_F64 && opts->precision != HB_MIXED)
+    return fail(HB_ERR_ARG, "precision must be HB_F64 or HB_MIXED");
+  if (opts->precision == HB_MIXED && opts->jv_kind == HB_JV_PAPER)
+    return fail(HB_ERR_ARG, "the mixed-precision solve uses the exact Jacobian");
+  if (opts->restart < 1 || opts->restart > 512) return fail(HB_ERR_ARG, "restart must be 1..512");
+  if (opts->max_newton < 0 || opts->max_gmres < 1) return fail(HB_ERR_ARG, "bad iteration limits");
+  if (!(opts->rtol > 0) || !(opts->gmres_eta > 0) || !(opts->cfl > 0) || !(opts->c1 >= 0))
+    return fail(HB_ERR_ARG, "rtol, gmres_eta, cfl must be positive");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = prepare(m, prm, bc, st);
+  if (rc) return rc;
+  if (opts->precision == HB_MIXED) return newton_run<float>(m, prm, bc, Y, opts, report, st, t0);
+  return newton_run<double>(m, prm, bc, Y, opts, report, st, t0);
 }
 
 }  // extern "C"

@@ -65,49 +65,62 @@ enum {
 // vectors carry 4 channels.
 constexpr int NCH = 7;
 
-hipError_t modal_to_samples(const DevMesh& m, int N, const double* Y, const double* dir,
-                            int zero_dirichlet, const double* tab, double* S, double* acc_zero,
+// Launchers.  Templates are instantiated for double, and for float where
+// the mixed-precision Krylov path needs them (directions, accumulators and
+// basis vectors in FP32; state, residual and preconditioner in FP64).
+template <typename TI, typename TO>
+hipError_t modal_to_samples(const DevMesh& m, int N, const TI* Y, const double* dir,
+                            int zero_dirichlet, const double* tab, TO* S, TO* acc_zero,
                             double* q_zero, int nq, hipStream_t st);
-hipError_t samples_to_modal(const DevMesh& m, int N, const double* acc, int use_z,
-                            int zero_dir_rows, int in_ch, const double* tab, double* R,
-                            hipStream_t st);
-hipError_t outlet_flux(const DevMesh& m, int N, const double* S, double* Q, hipStream_t st);
+template <typename TA, typename TO>
+hipError_t samples_to_modal(const DevMesh& m, int N, const TA* acc, int use_z, int zero_dir_rows,
+                            int in_ch, const double* tab, TO* R, hipStream_t st);
+template <typename R>
+hipError_t outlet_flux(const DevMesh& m, int N, const R* S, double* Q, hipStream_t st);
 hipError_t elem_residual(const DevMesh& m, const Phys& p, const double* S, double* acc,
                          const ElemBlocks& eb, hipStream_t st);
-hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
-                          double* acc, const ElemBlocks& eb, hipStream_t st);
+template <typename R>
+hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const R* Sy, const R* Sv, R* acc,
+                          const ElemBlocks& eb, hipStream_t st);
 hipError_t elem_jvp_paper(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
                           double* acc, hipStream_t st);
 hipError_t elem_jacobi(const DevMesh& m, const Phys& p, const double* Sy, double* dg,
                        int time_terms, hipStream_t st);
 hipError_t face_residual(const DevMesh& m, const Phys& p, const double* S, const double* hs,
                          const double* Rk, const double* Q, double* acc, hipStream_t st);
-hipError_t face_jvp(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
-                    const double* Rk, const double* dQ, double* acc, hipStream_t st);
+template <typename R>
+hipError_t face_jvp(const DevMesh& m, const Phys& p, const R* Sy, const R* Sv, const double* Rk,
+                    const double* dQ, R* acc, hipStream_t st);
 hipError_t jacobi_out(const DevMesh& m, int N, int nc, const double* dg, double* D, double* dinv,
                       hipStream_t st);
 // sample-space nodal passes (Krylov path)
-hipError_t prepare_direction(const DevMesh& m, int N, const double* q, int in_ch,
-                             const double* dinv, const double* binv, int zero_dirichlet,
-                             const double* tab, double* Sv, double* acc_zero, double* q_zero,
-                             int nq, hipStream_t st);
+template <typename TQ, typename TS>
+hipError_t prepare_direction(const DevMesh& m, int N, const TQ* q, int in_ch, const double* dinv,
+                             const double* binv, int zero_dirichlet, const double* tab, TS* Sv,
+                             TS* acc_zero, double* q_zero, int nq, hipStream_t st);
 // Per-node velocity time blocks of the exact Jacobian's nodal diagonal,
 // inverted in place: binv[a][s][k]; identity at Dirichlet nodes; dg with
 // 4 channels (K, L, T, X) from elem_jacobi(time_terms = 1).
 hipError_t block_factor(const DevMesh& m, int N, const double* dg, const double* mass,
                         double rho, const double* tab, double* binv, hipStream_t st);
-hipError_t finish_rows(const DevMesh& m, int N, const double* acc, int use_z, const double* tab,
-                       const double* id_rows, double* out, hipStream_t st);
+template <typename TA, typename TO>
+hipError_t finish_rows(const DevMesh& m, int N, const TA* acc, int use_z, const double* tab,
+                       const TO* id_rows, TO* out, hipStream_t st);
 // vectors
-hipError_t vec_dots(const double* Q, int64_t ld, int k, const double* w, int64_t L,
-                    double* partial, int nblk, double* out, hipStream_t st);
-hipError_t vec_axpy_multi(double* w, const double* Q, int64_t ld, int k, const double* h,
-                          double sign, int64_t L, hipStream_t st);
-hipError_t vec_scale(double* x, int64_t L, const double* inv_scalar, double s_host,
-                     hipStream_t st);
-hipError_t vec_copy_scaled(double* dst, const double* src, int64_t L, double s, hipStream_t st);
-hipError_t vec_zero(double* x, int64_t L, hipStream_t st);
-hipError_t vec_mul_dinv_add(double* y, const double* u, const double* dinv, const uint8_t* dmask,
+template <typename T>
+hipError_t vec_dots(const T* Q, int64_t ld, int k, const T* w, int64_t L, double* partial,
+                    int nblk, double* out, hipStream_t st);
+template <typename T>
+hipError_t vec_axpy_multi(T* w, const T* Q, int64_t ld, int k, const double* h, double sign,
+                          int64_t L, hipStream_t st);
+template <typename T>
+hipError_t vec_scale(T* x, int64_t L, double s, hipStream_t st);
+template <typename TD, typename TS>
+hipError_t vec_copy_scaled(TD* dst, const TS* src, int64_t L, double s, hipStream_t st);
+template <typename T>
+hipError_t vec_zero(T* x, int64_t L, hipStream_t st);
+template <typename TU>
+hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const uint8_t* dmask,
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st);
 hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st);
 

@@ -50,14 +50,18 @@ inline unsigned xcd_grid(int64_t nlogical) {
 }
 
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
-struct Geo {
-  double g[4][3];
-  double V, x00, x01, x02, x11, x12, x22, xixi;
+template <typename R>
+struct GeoT {
+  R g[4][3];
+  R V, x00, x01, x02, x11, x12, x22, xixi;
 };
+using Geo = GeoT<double>;
 
+template <typename R>
 __device__ __forceinline__ void load_geo(const double* __restrict__ geo, int64_t ne, int64_t t,
-                                         Geo& G) {
+                                         GeoT<R>& G) {
 #pragma unroll
   for (int A = 1; A < 4; ++A)
 #pragma unroll
@@ -74,7 +78,8 @@ __device__ __forceinline__ void load_geo(const double* __restrict__ geo, int64_t
   G.xixi = geo[GEO_XIXI * ne + t];
 }
 
-__device__ __forceinline__ void xi_mul(const Geo& G, const double u[3], double o[3]) {
+template <typename R>
+__device__ __forceinline__ void xi_mul(const GeoT<R>& G, const R u[3], R o[3]) {
   o[0] = G.x00 * u[0] + G.x01 * u[1] + G.x02 * u[2];
   o[1] = G.x01 * u[0] + G.x11 * u[1] + G.x12 * u[2];
   o[2] = G.x02 * u[0] + G.x12 * u[1] + G.x22 * u[2];
@@ -86,11 +91,12 @@ __device__ __forceinline__ void xi_mul(const Geo& G, const double u[3], double o
 // derivative of the velocity (H u).  Dirichlet velocity entries are replaced
 // by the boundary data (zero_dirichlet = 0) or by zero (= 1).  Optionally
 // clears the element accumulator of the tile and a short vector.
+template <typename TI, typename TO>
 __global__ void __launch_bounds__(BLK)
-k_modal_to_samples(int64_t n, int N, const double* __restrict__ Y, const double* __restrict__ dir,
+k_modal_to_samples(int64_t n, int N, const TI* __restrict__ Y, const double* __restrict__ dir,
                    const uint8_t* __restrict__ dmask, int zero_dirichlet,
-                   const double* __restrict__ tab, double* __restrict__ S,
-                   double* __restrict__ acc, double* __restrict__ qz, int nq) {
+                   const double* __restrict__ tab, TO* __restrict__ S,
+                   TO* __restrict__ acc, double* __restrict__ qz, int nq) {
   extern __shared__ double sm[];
   double* sY = sm;              // [4][N][TN]
   double* sB = sY + 4 * N * TN; // Binv [s][m]
@@ -108,14 +114,14 @@ k_modal_to_samples(int64_t n, int N, const double* __restrict__ Y, const double*
     double v = 0.0;
     if (al < tn) {
       const int64_t a = a0 + al;
-      v = Y[(int64_t)fm * n + a];
+      v = (double)Y[(int64_t)fm * n + a];
       if (fm < 3 * N && dmask[a]) v = zero_dirichlet ? 0.0 : dir[(int64_t)fm * n + a];
     }
     sY[i] = v;
   }
   if (acc) {
-    double* ap = acc + a0 * NCH * N;
-    for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) ap[i] = 0.0;
+    TO* ap = acc + a0 * NCH * N;
+    for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) ap[i] = TO(0);
   }
   if (qz && blockIdx.x == 0)
     for (int i = threadIdx.x; i < nq; i += BLK) qz[i] = 0.0;
@@ -132,19 +138,20 @@ k_modal_to_samples(int64_t n, int N, const double* __restrict__ Y, const double*
 #pragma unroll
       for (int f = 0; f < 3; ++f) o[4 + f] += d * sY[(f * N + m) * TN + al];
     }
-    double* out = S + (a0 + al) * NCH * N + s;
+    TO* out = S + (a0 + al) * NCH * N + s;
 #pragma unroll
-    for (int c = 0; c < 7; ++c) out[c * N] = o[c];
+    for (int c = 0; c < 7; ++c) out[c * N] = (TO)o[c];
   }
 }
 
 // Samples acc[a][c][s] -> modal R[f][m][a].  Momentum rows receive -H z,
 // i.e. -FwdD applied to the z channels (use_z), and are zeroed at Dirichlet
 // nodes when zero_dir_rows.
+template <typename TA, typename TO>
 __global__ void __launch_bounds__(BLK)
-k_samples_to_modal(int64_t n, int N, const double* __restrict__ acc, int use_z, int zero_dir_rows,
+k_samples_to_modal(int64_t n, int N, const TA* __restrict__ acc, int use_z, int zero_dir_rows,
                    int in_ch, const uint8_t* __restrict__ dmask, const double* __restrict__ tab,
-                   double* __restrict__ R) {
+                   TO* __restrict__ R) {
   extern __shared__ double sm[];
   const int CN = in_ch * N;
   double* sA = sm;              // [TN][in_ch][N]
@@ -157,8 +164,8 @@ k_samples_to_modal(int64_t n, int N, const double* __restrict__ acc, int use_z, 
     sF[i] = tab[TAB_FWD * NN + i];
     sG[i] = tab[TAB_FWDD * NN + i];
   }
-  const double* ap = acc + a0 * CN;
-  for (int i = threadIdx.x; i < tn * CN; i += BLK) sA[i] = ap[i];
+  const TA* ap = acc + a0 * CN;
+  for (int i = threadIdx.x; i < tn * CN; i += BLK) sA[i] = (double)ap[i];
   __syncthreads();
   for (int it = threadIdx.x; it < 4 * N * tn; it += BLK) {
     const int al = it % tn;
@@ -173,7 +180,7 @@ k_samples_to_modal(int64_t n, int N, const double* __restrict__ acc, int use_z, 
         for (int s = 0; s < N; ++s) v -= sG[m * N + s] * row[(4 + f) * N + s];
       if (zero_dir_rows && dmask[a0 + al]) v = 0.0;
     }
-    R[(int64_t)fm * n + a0 + al] = v;
+    R[(int64_t)fm * n + a0 + al] = (TO)v;
   }
 }
 
@@ -182,10 +189,11 @@ k_samples_to_modal(int64_t n, int N, const double* __restrict__ acc, int use_z, 
 // still dinv); velocity entries of Dirichlet nodes zeroed if zero_dirichlet.
 // Then Sv[a][0..3] = v and Sv[a][4..6] = H v.  q may alias Sv when
 // in_ch == NCH (state update in place).
+template <typename TQ, typename TS>
 __global__ void __launch_bounds__(BLK)
-k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict__ dinv,
+k_prepare(int64_t n, int N, const TQ* q, int in_ch, const double* __restrict__ dinv,
           const double* __restrict__ binv, int zero_dirichlet, const uint8_t* __restrict__ dmask,
-          const double* __restrict__ tab, double* Sv, double* __restrict__ acc,
+          const double* __restrict__ tab, TS* Sv, TS* __restrict__ acc,
           double* __restrict__ qz, int nq) {
   extern __shared__ double sm[];
   double* sV = sm;              // [TN][4][N]
@@ -201,7 +209,7 @@ k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict
     const int c = r / N;
     const int s = r - c * N;
     const int64_t a = a0 + al;
-    double v = q[(a * in_ch + c) * N + s];
+    double v = (double)q[(a * in_ch + c) * N + s];
     if (binv && c < 3) {
       sQ[(al * 3 + c) * N + s] = v;
     } else if (dinv) {
@@ -211,8 +219,8 @@ k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict
     sV[i] = v;
   }
   if (acc) {
-    double* ap = acc + a0 * NCH * N;
-    for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) ap[i] = 0.0;
+    TS* ap = acc + a0 * NCH * N;
+    for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) ap[i] = TS(0);
   }
   if (qz && blockIdx.x == 0)
     for (int i = threadIdx.x; i < nq; i += BLK) qz[i] = 0.0;
@@ -250,73 +258,90 @@ k_prepare(int64_t n, int N, const double* q, int in_ch, const double* __restrict
       h1 += hk * v[N + k];
       h2 += hk * v[2 * N + k];
     }
-    double* out = Sv + (a0 + al) * NCH * N + s;
-    out[0] = v[s];
-    out[N] = v[N + s];
-    out[2 * N] = v[2 * N + s];
-    out[3 * N] = v[3 * N + s];
-    out[4 * N] = h0;
-    out[5 * N] = h1;
-    out[6 * N] = h2;
+    TS* out = Sv + (a0 + al) * NCH * N + s;
+    out[0] = (TS)v[s];
+    out[N] = (TS)v[N + s];
+    out[2 * N] = (TS)v[2 * N + s];
+    out[3 * N] = (TS)v[3 * N + s];
+    out[4 * N] = (TS)h0;
+    out[5 * N] = (TS)h1;
+    out[6 * N] = (TS)h2;
   }
 }
 
-// One thread per node: the velocity block of the exact Jacobian's nodal
-// diagonal in time,
+// The velocity block of the exact Jacobian's nodal diagonal in time,
 //   B = diag(K_AA) + rho M_AA H + diag(X_AA) H - H diag(X_AA) - rho H diag(T_AA) H
 // (Galerkin time term, and the stabilisation's time terms: the test
 // function's -H N_A against tau L, with L's rho H u and rho u.grad u, and
-// the streamline test against tau rho H u), inverted in place by
-// Gauss-Jordan elimination without pivoting (the symmetric part of B is
-// diag(K_AA) + rho H^T diag(T_AA) H, positive).  Identity at Dirichlet
-// nodes.  dg has 4 channels (K, L, T, X).
-__global__ void __launch_bounds__(BLK)
+// the streamline test against tau rho H u), inverted by Gauss-Jordan
+// elimination without pivoting (the symmetric part of B is diag(K_AA) +
+// rho H^T diag(T_AA) H, positive).  One wavefront per node with the N x N
+// block in LDS; lane j owns column j.  Within a wavefront the
+// LDS accesses of one pivot step are ordered by program order, so no
+// barrier is needed between pivots.  Requires N <= 64 (one column per
+// lane).  Identity at Dirichlet nodes (and for the idle wavefront of a
+// ragged last workgroup).  dg has 4 channels (K, L, T, X).
+constexpr int FACT_WAVES = 2;
+__global__ void __launch_bounds__(64 * FACT_WAVES)
 k_block_factor(int64_t n, int N, const double* __restrict__ dg, const double* __restrict__ mass,
                double rho, const double* __restrict__ tab, const uint8_t* __restrict__ dmask,
                double* __restrict__ binv) {
-  const int64_t a = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  if (a >= n) return;
-  double* B = binv + a * N * N;
-  const double* H = tab + TAB_H * N * N;
-  const bool dir = dmask[a] != 0;
-  const double cm = rho * mass[a];
-  const double* Kd = dg + (a * 4) * N;
+  extern __shared__ double sm[];
+  const int NN = N * N;
+  double* sH = sm;
+  for (int i = threadIdx.x; i < NN; i += 64 * FACT_WAVES) sH[i] = tab[TAB_H * NN + i];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* B = sm + NN * (1 + wv);
+  const int64_t a = (int64_t)blockIdx.x * FACT_WAVES + wv;
+  const bool valid = a < n;
+  const bool ident = !valid || dmask[a] != 0;
+  const double* Kd = dg + (valid ? a : 0) * 4 * N;
   const double* Td = Kd + 2 * N;
   const double* Xd = Kd + 3 * N;
-  for (int s = 0; s < N; ++s)
-    for (int k = 0; k < N; ++k) {
-      if (dir) {
-        B[s * N + k] = (s == k) ? 1.0 : 0.0;
-        continue;
+  const double cm = valid ? rho * mass[a] : 0.0;
+  const int j = lane;
+  if (j < N)
+    for (int s = 0; s < N; ++s) {
+      double v;
+      if (ident) {
+        v = (s == j) ? 1.0 : 0.0;
+      } else {
+        v = (cm + Xd[s]) * sH[s * N + j] - sH[s * N + j] * Xd[j];
+        double h2 = 0.0;
+        for (int t = 0; t < N; ++t) h2 += sH[s * N + t] * Td[t] * sH[t * N + j];
+        v -= rho * h2;
+        if (s == j) v += Kd[s];
       }
-      double v = (cm + Xd[s]) * H[s * N + k] - H[s * N + k] * Xd[k];
-      double h2 = 0.0;
-      for (int t = 0; t < N; ++t) h2 += H[s * N + t] * Td[t] * H[t * N + k];
-      v -= rho * h2;
-      if (s == k) v += Kd[s];
-      B[s * N + k] = v;
+      B[s * N + j] = v;
     }
-  if (dir) return;
-  for (int k = 0; k < N; ++k) {
-    const double piv = B[k * N + k];
-    const double ip = 1.0 / piv;
-    B[k * N + k] = 1.0;
-    for (int j = 0; j < N; ++j) B[k * N + j] *= ip;
-    for (int i = 0; i < N; ++i) {
-      if (i == k) continue;
-      const double f = B[i * N + k];
-      B[i * N + k] = 0.0;
-      for (int j = 0; j < N; ++j) B[i * N + j] -= f * B[k * N + j];
+  for (int kp = 0; kp < N; ++kp) {
+    const double ip = 1.0 / B[kp * N + kp];
+    if (j < N) {
+      const double rk = (j == kp) ? ip : B[kp * N + j] * ip;
+      for (int i = 0; i < N; ++i) {
+        const double f = B[i * N + kp];
+        double nv;
+        if (i == kp)
+          nv = rk;
+        else
+          nv = (j == kp ? 0.0 : B[i * N + j]) - f * rk;
+        B[i * N + j] = nv;
+      }
     }
   }
+  if (!valid || j >= N) return;
+  double* out = binv + a * NN;
+  for (int s = 0; s < N; ++s) out[s * N + j] = B[s * N + j];
 }
 
 // Sample-space rows: out[a][i][s] = acc r^m_i - (H z_i) (use_z), out[a][3] =
 // r^c; Dirichlet momentum rows take id_rows (identity) or zero.
+template <typename TA, typename TO>
 __global__ void __launch_bounds__(BLK)
-k_finish(int64_t n, int N, const double* __restrict__ acc, int use_z,
+k_finish(int64_t n, int N, const TA* __restrict__ acc, int use_z,
          const uint8_t* __restrict__ dmask, const double* __restrict__ tab,
-         const double* __restrict__ id_rows, double* __restrict__ out) {
+         const TO* __restrict__ id_rows, TO* __restrict__ out) {
   extern __shared__ double sm[];
   double* sA = sm;                 // [TN][7][N]
   double* sH = sA + TN * NCH * N;
@@ -324,8 +349,8 @@ k_finish(int64_t n, int N, const double* __restrict__ acc, int use_z,
   const int tn = (int)min<int64_t>(TN, n - a0);
   const int NN = N * N;
   for (int i = threadIdx.x; i < NN; i += BLK) sH[i] = tab[TAB_H * NN + i];
-  const double* ap = acc + a0 * NCH * N;
-  for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) sA[i] = ap[i];
+  const TA* ap = acc + a0 * NCH * N;
+  for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) sA[i] = (double)ap[i];
   __syncthreads();
   for (int it = threadIdx.x; it < tn * 4 * N; it += BLK) {
     const int al = it / (4 * N);
@@ -340,9 +365,9 @@ k_finish(int64_t n, int N, const double* __restrict__ acc, int use_z,
         const double* z = row + (4 + c) * N;
         for (int k = 0; k < N; ++k) v -= sH[s * N + k] * z[k];
       }
-      if (dmask[a]) v = id_rows ? id_rows[(a * 4 + c) * N + s] : 0.0;
+      if (dmask[a]) v = id_rows ? (double)id_rows[(a * 4 + c) * N + s] : 0.0;
     }
-    out[(a * 4 + c) * N + s] = v;
+    out[(a * 4 + c) * N + s] = (TO)v;
   }
 }
 
@@ -375,29 +400,48 @@ __device__ __forceinline__ void scatter_rows(double* __restrict__ acc, const int
 // nodes; a reduce-scatter across the quad leaves lane A with node A's seven
 // rows, which it adds to the accumulator with seven atomics.
 
-__device__ __forceinline__ double quad_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
+// Exchange with the lane whose index differs in bit 0 (CTRL = 0xB1, quad
+// permutation [1,0,3,2]) or bit 1 (CTRL = 0x4E, [2,3,0,1]) through DPP
+// moves, which stay in the vector ALU (no LDS crossbar traffic).  All four
+// lanes of a quad are always active together.
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+constexpr int XOR1 = 0xB1, XOR2 = 0x4E;
+
+template <typename R>
+__device__ __forceinline__ R quad_sum(R v) {
+  v += quad_swap<XOR1>(v);
+  v += quad_swap<XOR2>(v);
   return v;
 }
 
 // cr[B][c] (contributions of this lane to node B, channel c) -> the sum
 // over the quad of cr[A][c] for this lane's A.
-__device__ __forceinline__ void quad_reduce_scatter(int A, double cr[4][NCH], double out[NCH]) {
+template <typename R>
+__device__ __forceinline__ void quad_reduce_scatter(int A, R cr[4][NCH], R out[NCH]) {
   const bool hi = (A & 2) != 0, lo = (A & 1) != 0;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    const double k0 = hi ? cr[2][c] : cr[0][c];
-    const double k1 = hi ? cr[3][c] : cr[1][c];
-    const double s0 = hi ? cr[0][c] : cr[2][c];
-    const double s1 = hi ? cr[1][c] : cr[3][c];
-    const double r0 = k0 + __shfl_xor(s0, 2);
-    const double r1 = k1 + __shfl_xor(s1, 2);
-    out[c] = (lo ? r1 : r0) + __shfl_xor(lo ? r0 : r1, 1);
+    const R k0 = hi ? cr[2][c] : cr[0][c];
+    const R k1 = hi ? cr[3][c] : cr[1][c];
+    const R s0 = hi ? cr[0][c] : cr[2][c];
+    const R s1 = hi ? cr[1][c] : cr[3][c];
+    const R r0 = k0 + quad_swap<XOR2>(s0);
+    const R r1 = k1 + quad_swap<XOR2>(s1);
+    out[c] = (lo ? r1 : r0) + quad_swap<XOR1>(lo ? r0 : r1);
   }
 }
 
-__device__ __forceinline__ void pick_grad(const Geo& G, int A, double g[3]) {
+template <typename R>
+__device__ __forceinline__ void pick_grad(const GeoT<R>& G, int A, R g[3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     g[i] = A == 0 ? G.g[0][i] : A == 1 ? G.g[1][i] : A == 2 ? G.g[2][i] : G.g[3][i];
@@ -475,19 +519,20 @@ __device__ __forceinline__ int64_t residual_lane(const DevMesh& m, const Phys& p
 // Exact directional derivative of k_elem_residual along the direction
 // samples Sv (dtau = -tau^3 u.xi du from eq. tau), plus shift * int N_A N_B
 // on the velocity rows.
+template <typename R>
 __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& p,
-                                                  const double* __restrict__ Sy,
-                                                  const double* __restrict__ Sv, int64_t t, int s,
-                                                  int A, double res[NCH]) {
+                                                  const R* __restrict__ Sy,
+                                                  const R* __restrict__ Sv, int64_t t, int s,
+                                                  int A, R res[NCH]) {
   const int N = p.N;
-  Geo G;
+  GeoT<R> G;
   load_geo(m.geo, m.ne, t, G);
-  double gA[3];
+  R gA[3];
   pick_grad(G, A, gA);
   const int64_t base = (int64_t)m.tets[A * m.ne + t] * NCH * N + s;
-  const double* q = Sy + base;
-  const double* d = Sv + base;
-  double u[3], hu[3], du[3], dhu[3];
+  const R* q = Sy + base;
+  const R* d = Sv + base;
+  R u[3], hu[3], du[3], dhu[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     u[i] = q[i * N];
@@ -495,8 +540,8 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
     du[i] = d[i * N];
     dhu[i] = d[(4 + i) * N];
   }
-  const double pr = q[3 * N], dp = d[3 * N];
-  double Gm[3][3], dG[3][3], gp[3], dgp[3], uq[3], hq[3], duq[3], dhq[3], dus[3];
+  const R pr = q[3 * N], dp = d[3 * N];
+  R Gm[3][3], dG[3][3], gp[3], dgp[3], uq[3], hq[3], duq[3], dhq[3], dus[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
 #pragma unroll
@@ -507,15 +552,15 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
     gp[i] = quad_sum(pr * gA[i]);
     dgp[i] = quad_sum(dp * gA[i]);
     dus[i] = quad_sum(du[i]);
-    uq[i] = QB * quad_sum(u[i]) + (QA - QB) * u[i];
-    hq[i] = QB * quad_sum(hu[i]) + (QA - QB) * hu[i];
-    duq[i] = QB * dus[i] + (QA - QB) * du[i];
-    dhq[i] = QB * quad_sum(dhu[i]) + (QA - QB) * dhu[i];
+    uq[i] = R(QB) * quad_sum(u[i]) + R(QA - QB) * u[i];
+    hq[i] = R(QB) * quad_sum(hu[i]) + R(QA - QB) * hu[i];
+    duq[i] = R(QB) * dus[i] + R(QA - QB) * du[i];
+    dhq[i] = R(QB) * quad_sum(dhu[i]) + R(QA - QB) * dhu[i];
   }
-  const double dpbar = 0.25 * quad_sum(dp);
-  const double rho = p.rho;
-  const double w = 0.25 * G.V;
-  double adv[3], dadv[3], xu[3];
+  const R dpbar = R(0.25) * quad_sum(dp);
+  const R rho = (R)p.rho;
+  const R w = R(0.25) * G.V;
+  R adv[3], dadv[3], xu[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
@@ -523,23 +568,23 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
             + uq[0] * dG[i][0] + uq[1] * dG[i][1] + uq[2] * dG[i][2];
   }
   xi_mul(G, uq, xu);
-  const double tau =
-      1.0 / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + p.C_I * p.nu * p.nu * G.xixi);
-  const double dtau = -tau * tau * tau * (xu[0] * duq[0] + xu[1] * duq[1] + xu[2] * duq[2]);
-  double sv[3], ds[3], dgal[3];
+  const R tau =
+      R(1) / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + R(p.C_I * p.nu * p.nu) * G.xixi);
+  const R dtau = -tau * tau * tau * (xu[0] * duq[0] + xu[1] * duq[1] + xu[2] * duq[2]);
+  R sv[3], ds[3], dgal[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const double L = rho * (hq[i] + adv[i]) + gp[i];
+    const R L = rho * (hq[i] + adv[i]) + gp[i];
     dgal[i] = rho * (dhq[i] + dadv[i]);
     sv[i] = tau * L;
     ds[i] = dtau * L + tau * (dgal[i] + dgp[i]);
   }
-  double cr[4][NCH];
+  R cr[4][NCH];
 #pragma unroll
   for (int B = 0; B < 4; ++B) {
-    const double NB = (B == A) ? QA : QB;
-    const double c = uq[0] * G.g[B][0] + uq[1] * G.g[B][1] + uq[2] * G.g[B][2];
-    const double dc = duq[0] * G.g[B][0] + duq[1] * G.g[B][1] + duq[2] * G.g[B][2];
+    const R NB = (B == A) ? R(QA) : R(QB);
+    const R c = uq[0] * G.g[B][0] + uq[1] * G.g[B][1] + uq[2] * G.g[B][2];
+    const R dc = duq[0] * G.g[B][0] + duq[1] * G.g[B][1] + duq[2] * G.g[B][2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       cr[B][i] = w * (NB * dgal[i] + dc * sv[i] + c * ds[i]);
@@ -548,11 +593,11 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
     cr[B][3] = w * (G.g[B][0] * ds[0] + G.g[B][1] * ds[1] + G.g[B][2] * ds[2]) / rho;
   }
   quad_reduce_scatter(A, cr, res);
-  const double V = G.V;
-  const double ms = p.shift * V * (1.0 / 20.0);
+  const R V = G.V;
+  const R ms = R(p.shift) * V * R(1.0 / 20.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
-    res[i] += V * (p.mu * (gA[0] * dG[i][0] + gA[1] * dG[i][1] + gA[2] * dG[i][2]) - gA[i] * dpbar)
+    res[i] += V * (R(p.mu) * (gA[0] * dG[i][0] + gA[1] * dG[i][1] + gA[2] * dG[i][2]) - gA[i] * dpbar)
             + ms * (dus[i] + du[i]);
   res[3] += w * (dG[0][0] + dG[1][1] + dG[2][2]);
   return base;
@@ -565,11 +610,12 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
 // accumulator once (contiguous atomics), instead of one atomic per element
 // row.  Device-scope FP64 atomics are resolved beyond the per-XCD L2, so
 // their count is what this removes.
-template <int KIND>
+template <int KIND, typename R>
 __global__ void __launch_bounds__(BLK)
-k_elem_block(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __restrict__ Sv,
-             double* __restrict__ acc, ElemBlocks eb, int64_t nlogical) {
-  extern __shared__ double sacc[];  // [U][NCH][N]
+k_elem_block(DevMesh m, Phys p, const R* __restrict__ Sy, const R* __restrict__ Sv,
+             R* __restrict__ acc, ElemBlocks eb, int64_t nlogical) {
+  extern __shared__ double smem[];
+  R* sacc = reinterpret_cast<R*>(smem);  // [U][NCH][N]
   const int64_t b = xcd_block(nlogical);
   if (b < 0) return;
   const int N = p.N;
@@ -578,7 +624,7 @@ k_elem_block(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __r
   const int nel = (int)min<int64_t>(eb.size, m.ne - e0);
   const int32_t p0 = eb.ptr[b];
   const int U = eb.ptr[b + 1] - p0;
-  for (int i = threadIdx.x; i < U * CN; i += BLK) sacc[i] = 0.0;
+  for (int i = threadIdx.x; i < U * CN; i += BLK) sacc[i] = R(0);
   __syncthreads();
   const int total = nel * N * 4;
   for (int it = threadIdx.x; it < total; it += BLK) {  // quads stay aligned (BLK % 4 == 0)
@@ -587,12 +633,12 @@ k_elem_block(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __r
     const int el = ts / N;
     const int s = ts - el * N;
     const int64_t t = e0 + el;
-    double r[NCH];
-    if (KIND == 0)
+    R r[NCH];
+    if constexpr (KIND == 0)
       residual_lane(m, p, Sy, t, s, A, r);
     else
-      jvp_exact_lane(m, p, Sy, Sv, t, s, A, r);
-    double* dst = sacc + eb.slot[A * m.ne + t] * CN + s;
+      jvp_exact_lane<R>(m, p, Sy, Sv, t, s, A, r);
+    R* dst = sacc + eb.slot[A * m.ne + t] * CN + s;
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
       __hip_atomic_fetch_add(dst + c * N, r[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -774,8 +820,9 @@ k_elem_jacobi(DevMesh m, Phys p, const double* __restrict__ Sy, double* __restri
 
 // Q[k][s] = sum over outlet k's faces of area * (mean nodal u) . n; one
 // workgroup per sample, per-outlet partial sums in LDS.
+template <typename R>
 __global__ void __launch_bounds__(BLK)
-k_outlet_flux(DevMesh m, int N, const double* __restrict__ S, double* __restrict__ Q) {
+k_outlet_flux(DevMesh m, int N, const R* __restrict__ S, double* __restrict__ Q) {
   __shared__ double sq[64];
   const int s = blockIdx.x;
   for (int k = threadIdx.x; k < m.n_out; k += BLK) sq[k] = 0.0;
@@ -784,7 +831,7 @@ k_outlet_flux(DevMesh m, int N, const double* __restrict__ S, double* __restrict
     double ub[3] = {0, 0, 0};
 #pragma unroll
     for (int A = 0; A < 3; ++A) {
-      const double* q = S + (int64_t)m.of[A * m.nof + f] * NCH * N + s;
+      const R* q = S + (int64_t)m.of[A * m.nof + f] * NCH * N + s;
       ub[0] += q[0];
       ub[1] += q[N];
       ub[2] += q[2 * N];
@@ -852,9 +899,10 @@ k_face_residual(DevMesh m, Phys p, const double* __restrict__ S, const double* _
 
 // Directional derivative of k_face_residual: -int N_A (-R dQ) n_i and the
 // backflow tangent with the kink's derivative taken as zero at u.n = 0.
+template <typename R>
 __global__ void __launch_bounds__(BLK)
-k_face_jvp(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __restrict__ Sv,
-           const double* __restrict__ Rk, const double* __restrict__ dQ, double* __restrict__ acc) {
+k_face_jvp(DevMesh m, Phys p, const R* __restrict__ Sy, const R* __restrict__ Sv,
+           const double* __restrict__ Rk, const double* __restrict__ dQ, R* __restrict__ acc) {
   const int N = p.N;
   const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
   if (gid >= m.nof * N) return;
@@ -904,7 +952,7 @@ k_face_jvp(DevMesh m, Phys p, const double* __restrict__ Sy, const double* __res
 #pragma unroll
   for (int A = 0; A < 3; ++A)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) atomic_add(acc + base[A] + i * N, r[A][i]);
+    for (int i = 0; i < 3; ++i) atomic_add(acc + base[A] + i * N, (R)r[A][i]);
 }
 
 // dg[a][c][s] -> D[c][s][a] (field-major), Dirichlet velocity rows = 1;
@@ -928,9 +976,9 @@ k_jacobi_out(int64_t n, int N, int nc, const uint8_t* __restrict__ dmask, double
 
 // -------------------------------------------------------------- vectors
 
-template <int G>
+template <int G, typename T>
 __global__ void __launch_bounds__(BLK)
-k_dots(const double* __restrict__ Q, int64_t ld, int k0, int kc, const double* __restrict__ w,
+k_dots(const T* __restrict__ Q, int64_t ld, int k0, int kc, const T* __restrict__ w,
        int64_t L, double* __restrict__ partial, int nblk) {
   __shared__ double red[G][BLK / 64];
   double acc[G];
@@ -938,10 +986,10 @@ k_dots(const double* __restrict__ Q, int64_t ld, int k0, int kc, const double* _
   for (int j = 0; j < G; ++j) acc[j] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * BLK;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) {
-    const double wi = w[i];
+    const double wi = (double)w[i];
 #pragma unroll
     for (int j = 0; j < G; ++j)
-      if (j < kc) acc[j] += Q[(int64_t)(k0 + j) * ld + i] * wi;
+      if (j < kc) acc[j] += (double)Q[(int64_t)(k0 + j) * ld + i] * wi;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -978,39 +1026,46 @@ k_reduce_rows(const double* __restrict__ partial, int nblk, double* __restrict__
   }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(BLK)
-k_axpy_multi(double* __restrict__ w, const double* __restrict__ Q, int64_t ld, int k,
+k_axpy_multi(T* __restrict__ w, const T* __restrict__ Q, int64_t ld, int k,
              const double* __restrict__ h, double sign, int64_t L) {
   const int64_t stride = (int64_t)gridDim.x * BLK;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) {
     double v = 0.0;
-    for (int j = 0; j < k; ++j) v += h[j] * Q[(int64_t)j * ld + i];
-    w[i] += sign * v;
+    for (int j = 0; j < k; ++j) v += h[j] * (double)Q[(int64_t)j * ld + i];
+    w[i] = (T)((double)w[i] + sign * v);
   }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(BLK)
-k_scale(double* __restrict__ x, int64_t L, double s) {
+k_scale(T* __restrict__ x, int64_t L, double s) {
   const int64_t stride = (int64_t)gridDim.x * BLK;
-  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) x[i] *= s;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride)
+    x[i] = (T)((double)x[i] * s);
 }
 
+template <typename T>
 __global__ void __launch_bounds__(BLK)
-k_fill(double* __restrict__ x, int64_t L, double v) {
+k_fill(T* __restrict__ x, int64_t L, double v) {
   const int64_t stride = (int64_t)gridDim.x * BLK;
-  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) x[i] = v;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) x[i] = (T)v;
 }
 
+template <typename TD, typename TS>
 __global__ void __launch_bounds__(BLK)
-k_copy_scaled(double* __restrict__ d, const double* __restrict__ x, int64_t L, double s) {
+k_copy_scaled(TD* __restrict__ d, const TS* __restrict__ x, int64_t L, double s) {
   const int64_t stride = (int64_t)gridDim.x * BLK;
-  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) d[i] = s * x[i];
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride)
+    d[i] = (TD)(s * (double)x[i]);
 }
 
 // y[a][c][s] += s * dinv[a][c<3?0:1][s] * u[a][c][s] for c < 4, skipping the
 // velocity entries of Dirichlet nodes.  y has nch_y channels per node.
+template <typename TU>
 __global__ void __launch_bounds__(BLK)
-k_mul_dinv_add(double* __restrict__ y, const double* __restrict__ u,
+k_mul_dinv_add(double* __restrict__ y, const TU* __restrict__ u,
                const double* __restrict__ dinv, const uint8_t* __restrict__ dmask, int64_t n,
                int N, int nch_y, int nch_u, double s) {
   const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
@@ -1021,7 +1076,7 @@ k_mul_dinv_add(double* __restrict__ y, const double* __restrict__ u,
   const int sm = r - c * N;
   if (c < 3 && dmask[a]) return;
   const double d = dinv ? dinv[(a * 2 + (c < 3 ? 0 : 1)) * N + sm] : 1.0;
-  y[(a * nch_y + c) * N + sm] += s * d * u[(a * nch_u + c) * N + sm];
+  y[(a * nch_y + c) * N + sm] += s * d * (double)u[(a * nch_u + c) * N + sm];
 }
 
 __global__ void __launch_bounds__(BLK)
@@ -1044,54 +1099,59 @@ inline unsigned stream_blocks(int64_t L) {
 
 // ------------------------------------------------------------- launchers
 
-hipError_t modal_to_samples(const DevMesh& m, int N, const double* Y, const double* dir,
-                            int zero_dirichlet, const double* tab, double* S, double* acc_zero,
+template <typename TI, typename TO>
+hipError_t modal_to_samples(const DevMesh& m, int N, const TI* Y, const double* dir,
+                            int zero_dirichlet, const double* tab, TO* S, TO* acc_zero,
                             double* q_zero, int nq, hipStream_t st) {
   if (m.n == 0) return hipSuccess;
   const size_t lds = sizeof(double) * (4 * N * TN + 2 * N * N);
-  hipLaunchKernelGGL(k_modal_to_samples, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, Y, dir,
-                     m.dmask, zero_dirichlet, tab, S, acc_zero, q_zero, nq);
+  hipLaunchKernelGGL((k_modal_to_samples<TI, TO>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N,
+                     Y, dir, m.dmask, zero_dirichlet, tab, S, acc_zero, q_zero, nq);
   return hipGetLastError();
 }
 
-hipError_t samples_to_modal(const DevMesh& m, int N, const double* acc, int use_z,
-                            int zero_dir_rows, int in_ch, const double* tab, double* R,
-                            hipStream_t st) {
+template <typename TA, typename TO>
+hipError_t samples_to_modal(const DevMesh& m, int N, const TA* acc, int use_z, int zero_dir_rows,
+                            int in_ch, const double* tab, TO* R, hipStream_t st) {
   if (m.n == 0) return hipSuccess;
   const size_t lds = sizeof(double) * (TN * in_ch * N + 2 * N * N);
-  hipLaunchKernelGGL(k_samples_to_modal, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, acc, use_z,
-                     zero_dir_rows, in_ch, m.dmask, tab, R);
+  hipLaunchKernelGGL((k_samples_to_modal<TA, TO>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N,
+                     acc, use_z, zero_dir_rows, in_ch, m.dmask, tab, R);
   return hipGetLastError();
 }
 
-hipError_t prepare_direction(const DevMesh& m, int N, const double* q, int in_ch,
-                             const double* dinv, const double* binv, int zero_dirichlet,
-                             const double* tab, double* Sv, double* acc_zero, double* q_zero,
-                             int nq, hipStream_t st) {
+template <typename TQ, typename TS>
+hipError_t prepare_direction(const DevMesh& m, int N, const TQ* q, int in_ch, const double* dinv,
+                             const double* binv, int zero_dirichlet, const double* tab, TS* Sv,
+                             TS* acc_zero, double* q_zero, int nq, hipStream_t st) {
   const size_t lds = sizeof(double) * (TN * 4 * N + N * N + (binv ? TN * 3 * N : 0));
-  hipLaunchKernelGGL(k_prepare, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, q, in_ch, dinv,
-                     binv, zero_dirichlet, m.dmask, tab, Sv, acc_zero, q_zero, nq);
+  hipLaunchKernelGGL((k_prepare<TQ, TS>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, q, in_ch,
+                     dinv, binv, zero_dirichlet, m.dmask, tab, Sv, acc_zero, q_zero, nq);
   return hipGetLastError();
 }
 
 hipError_t block_factor(const DevMesh& m, int N, const double* dg, const double* mass,
                         double rho, const double* tab, double* binv, hipStream_t st) {
-  hipLaunchKernelGGL(k_block_factor, dim3(blocks_for(m.n)), dim3(BLK), 0, st, m.n, N, dg, mass,
+  const size_t lds = sizeof(double) * (size_t)N * N * (1 + FACT_WAVES);
+  const unsigned grid = (unsigned)((m.n + FACT_WAVES - 1) / FACT_WAVES);
+  hipLaunchKernelGGL(k_block_factor, dim3(grid), dim3(64 * FACT_WAVES), lds, st, m.n, N, dg, mass,
                      rho, tab, m.dmask, binv);
   return hipGetLastError();
 }
 
-hipError_t finish_rows(const DevMesh& m, int N, const double* acc, int use_z, const double* tab,
-                       const double* id_rows, double* out, hipStream_t st) {
+template <typename TA, typename TO>
+hipError_t finish_rows(const DevMesh& m, int N, const TA* acc, int use_z, const double* tab,
+                       const TO* id_rows, TO* out, hipStream_t st) {
   const size_t lds = sizeof(double) * (TN * NCH * N + N * N);
-  hipLaunchKernelGGL(k_finish, dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, acc, use_z, m.dmask,
-                     tab, id_rows, out);
+  hipLaunchKernelGGL((k_finish<TA, TO>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, acc, use_z,
+                     m.dmask, tab, id_rows, out);
   return hipGetLastError();
 }
 
-hipError_t outlet_flux(const DevMesh& m, int N, const double* S, double* Q, hipStream_t st) {
+template <typename R>
+hipError_t outlet_flux(const DevMesh& m, int N, const R* S, double* Q, hipStream_t st) {
   if (m.nof == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_outlet_flux, dim3(N), dim3(BLK), 0, st, m, N, S, Q);
+  hipLaunchKernelGGL((k_outlet_flux<R>), dim3(N), dim3(BLK), 0, st, m, N, S, Q);
   return hipGetLastError();
 }
 
@@ -1099,17 +1159,18 @@ hipError_t elem_residual(const DevMesh& m, const Phys& p, const double* S, doubl
                          const ElemBlocks& eb, hipStream_t st) {
   const int64_t nb = (m.ne + eb.size - 1) / eb.size;
   const size_t lds = sizeof(double) * (size_t)eb.max_unique * NCH * p.N;
-  hipLaunchKernelGGL(k_elem_block<0>, dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, S, S, acc, eb,
-                     nb);
+  hipLaunchKernelGGL((k_elem_block<0, double>), dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, S, S,
+                     acc, eb, nb);
   return hipGetLastError();
 }
 
-hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
-                          double* acc, const ElemBlocks& eb, hipStream_t st) {
+template <typename R>
+hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const R* Sy, const R* Sv, R* acc,
+                          const ElemBlocks& eb, hipStream_t st) {
   const int64_t nb = (m.ne + eb.size - 1) / eb.size;
-  const size_t lds = sizeof(double) * (size_t)eb.max_unique * NCH * p.N;
-  hipLaunchKernelGGL(k_elem_block<1>, dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, Sy, Sv, acc,
-                     eb, nb);
+  const size_t lds = sizeof(R) * (size_t)eb.max_unique * NCH * p.N;
+  hipLaunchKernelGGL((k_elem_block<1, R>), dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, Sy, Sv,
+                     acc, eb, nb);
   return hipGetLastError();
 }
 
@@ -1137,11 +1198,12 @@ hipError_t face_residual(const DevMesh& m, const Phys& p, const double* S, const
   return hipGetLastError();
 }
 
-hipError_t face_jvp(const DevMesh& m, const Phys& p, const double* Sy, const double* Sv,
-                    const double* Rk, const double* dQ, double* acc, hipStream_t st) {
+template <typename R>
+hipError_t face_jvp(const DevMesh& m, const Phys& p, const R* Sy, const R* Sv, const double* Rk,
+                    const double* dQ, R* acc, hipStream_t st) {
   if (m.nof == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_face_jvp, dim3(blocks_for(m.nof * p.N)), dim3(BLK), 0, st, m, p, Sy, Sv,
-                     Rk, dQ, acc);
+  hipLaunchKernelGGL((k_face_jvp<R>), dim3(blocks_for(m.nof * p.N)), dim3(BLK), 0, st, m, p, Sy,
+                     Sv, Rk, dQ, acc);
   return hipGetLastError();
 }
 
@@ -1152,43 +1214,50 @@ hipError_t jacobi_out(const DevMesh& m, int N, int nc, const double* dg, double*
   return hipGetLastError();
 }
 
-hipError_t vec_dots(const double* Q, int64_t ld, int k, const double* w, int64_t L,
-                    double* partial, int nblk, double* out, hipStream_t st) {
+template <typename T>
+hipError_t vec_dots(const T* Q, int64_t ld, int k, const T* w, int64_t L, double* partial,
+                    int nblk, double* out, hipStream_t st) {
   for (int k0 = 0; k0 < k; k0 += 8) {
     const int kc = k - k0 < 8 ? k - k0 : 8;
-    hipLaunchKernelGGL(k_dots<8>, dim3(nblk), dim3(BLK), 0, st, Q, ld, k0, kc, w, L, partial,
+    hipLaunchKernelGGL((k_dots<8, T>), dim3(nblk), dim3(BLK), 0, st, Q, ld, k0, kc, w, L, partial,
                        nblk);
   }
   hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(BLK), 0, st, partial, nblk, out);
   return hipGetLastError();
 }
 
-hipError_t vec_axpy_multi(double* w, const double* Q, int64_t ld, int k, const double* h,
-                          double sign, int64_t L, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_multi, dim3(stream_blocks(L)), dim3(BLK), 0, st, w, Q, ld, k, h, sign,
-                     L);
+template <typename T>
+hipError_t vec_axpy_multi(T* w, const T* Q, int64_t ld, int k, const double* h, double sign,
+                          int64_t L, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy_multi<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, w, Q, ld, k, h,
+                     sign, L);
   return hipGetLastError();
 }
 
-hipError_t vec_scale(double* x, int64_t L, const double*, double s_host, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale, dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, s_host);
+template <typename T>
+hipError_t vec_scale(T* x, int64_t L, double s, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, s);
   return hipGetLastError();
 }
 
-hipError_t vec_copy_scaled(double* dst, const double* src, int64_t L, double s, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy_scaled, dim3(stream_blocks(L)), dim3(BLK), 0, st, dst, src, L, s);
+template <typename TD, typename TS>
+hipError_t vec_copy_scaled(TD* dst, const TS* src, int64_t L, double s, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_scaled<TD, TS>), dim3(stream_blocks(L)), dim3(BLK), 0, st, dst, src,
+                     L, s);
   return hipGetLastError();
 }
 
-hipError_t vec_zero(double* x, int64_t L, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill, dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, 0.0);
+template <typename T>
+hipError_t vec_zero(T* x, int64_t L, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, 0.0);
   return hipGetLastError();
 }
 
-hipError_t vec_mul_dinv_add(double* y, const double* u, const double* dinv, const uint8_t* dmask,
+template <typename TU>
+hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const uint8_t* dmask,
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st) {
-  hipLaunchKernelGGL(k_mul_dinv_add, dim3(blocks_for(n * 4 * N)), dim3(BLK), 0, st, y, u, dinv,
-                     dmask, n, N, nch_y, nch_u, s);
+  hipLaunchKernelGGL((k_mul_dinv_add<TU>), dim3(blocks_for(n * 4 * N)), dim3(BLK), 0, st, y, u,
+                     dinv, dmask, n, N, nch_y, nch_u, s);
   return hipGetLastError();
 }
 
@@ -1196,5 +1265,44 @@ hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st) 
   hipLaunchKernelGGL(k_nonfinite, dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, flag);
   return hipGetLastError();
 }
+
+// explicit instantiations: FP64 everywhere, FP32 for the mixed-precision
+// Krylov path (FP32 directions, accumulators and basis vectors).
+#define HB_INST_IO(TI, TO)                                                                      \
+  template hipError_t modal_to_samples<TI, TO>(const DevMesh&, int, const TI*, const double*,  \
+                                               int, const double*, TO*, TO*, double*, int,      \
+                                               hipStream_t);                                    \
+  template hipError_t samples_to_modal<TI, TO>(const DevMesh&, int, const TI*, int, int, int,  \
+                                               const double*, TO*, hipStream_t);                \
+  template hipError_t prepare_direction<TI, TO>(const DevMesh&, int, const TI*, int,           \
+                                                const double*, const double*, int,              \
+                                                const double*, TO*, TO*, double*, int,          \
+                                                hipStream_t);                                   \
+  template hipError_t finish_rows<TI, TO>(const DevMesh&, int, const TI*, int, const double*,  \
+                                          const TO*, TO*, hipStream_t);                         \
+  template hipError_t vec_copy_scaled<TI, TO>(TI*, const TO*, int64_t, double, hipStream_t);
+HB_INST_IO(double, double)
+HB_INST_IO(double, float)
+HB_INST_IO(float, float)
+HB_INST_IO(float, double)
+#undef HB_INST_IO
+
+#define HB_INST_T(T)                                                                            \
+  template hipError_t outlet_flux<T>(const DevMesh&, int, const T*, double*, hipStream_t);     \
+  template hipError_t elem_jvp_exact<T>(const DevMesh&, const Phys&, const T*, const T*, T*,   \
+                                        const ElemBlocks&, hipStream_t);                        \
+  template hipError_t face_jvp<T>(const DevMesh&, const Phys&, const T*, const T*,             \
+                                  const double*, const double*, T*, hipStream_t);               \
+  template hipError_t vec_dots<T>(const T*, int64_t, int, const T*, int64_t, double*, int,     \
+                                  double*, hipStream_t);                                        \
+  template hipError_t vec_axpy_multi<T>(T*, const T*, int64_t, int, const double*, double,     \
+                                        int64_t, hipStream_t);                                  \
+  template hipError_t vec_scale<T>(T*, int64_t, double, hipStream_t);                           \
+  template hipError_t vec_zero<T>(T*, int64_t, hipStream_t);                                    \
+  template hipError_t vec_mul_dinv_add<T>(double*, const T*, const double*, const uint8_t*,    \
+                                          int64_t, int, int, int, double, hipStream_t);
+HB_INST_T(double)
+HB_INST_T(float)
+#undef HB_INST_T
 
 }  // namespace hb

@@ -150,7 +150,7 @@ def test_solve_matches_oracle_solution(c1):
     P = c1.P
     Y = dev(g["Y0"])
     rep = hbl.newton_solve(c1.gm, P.params, c1.bc, Y,
-                           hbl.SolveOptions(rtol=1e-12, max_newton=40, max_gmres=2000))
+                           hbl.SolveOptions(rtol=1e-12, max_newton=400, max_gmres=1000))
     assert rep["status"] == 0
     Yg = host(Y)
     assert rel(Yg, g["Y"]) <= TOL
@@ -173,3 +173,34 @@ def test_solve_error_paths(c1):
     with pytest.raises(hbl.HBError) as e:
         hbl.residual(c1.gm, Params(K=40), c1.bc, dev(seeded_state(P, 0)))
     assert e.value.status == hbl.HB_ERR_ARG
+
+
+# FP32 Jacobian-vector products (mixed-precision path).  Tolerance: FP32 unit
+# roundoff 6e-8, times the cancellation in the assembled rows (sum of |terms|
+# over |sum| up to ~1e2 at these states), times ~10 rounding steps per term:
+# 6e-5; the bar is 1e-4 relative L2 against the FP64 oracle.
+TOL_F32 = 1e-4
+
+
+@pytest.mark.parametrize("case", ["c1", "tj"])
+def test_jvp_f32_parity(case, request):
+    c = request.getfixturevalue(case)
+    Y = seeded_state(c.P, 13)
+    V = seeded_state(c.P, 14)
+    om, prm, d, h, R = c.args()
+    ref = api.jvp_modal(om, prm, Y, V, d, h, R)
+    got = host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V).float())).astype(np.float64)
+    assert rel(got, ref) <= TOL_F32
+
+
+def test_mixed_solve_matches_oracle_solution(c1):
+    """FP32 Krylov basis and Jv with the FP64 residual as the outer loop
+    reach the same FP64 root."""
+    g = np.load(os.path.join(HERE, "golden", "c1_solution.npz"))
+    P = c1.P
+    Y = dev(g["Y0"])
+    rep = hbl.newton_solve(c1.gm, P.params, c1.bc, Y,
+                           hbl.SolveOptions(rtol=1e-12, max_newton=400, max_gmres=1000,
+                                            precision=hbl.HB_MIXED))
+    assert rep["status"] == 0
+    assert rel(host(Y), g["Y"]) <= TOL
