@@ -123,6 +123,53 @@ def womersley_time_to_solution(hbl, torch, log, precision="fp64"):
     return res
 
 
+def learned_warm_start(torch, log, n_train, n_test, K=2):
+    """Learned warm start on the stenosed-pipe family (925 nodes, Womersley
+    number 4, severity up to 50 %): n_train solutions generated by the
+    solver (batched as disjoint-union meshes), POD + MLP trained on the GPU,
+    then plain vs learned start on n_test held-out draws to 1e-8 of the
+    plain start's residual.  Times include the steady start (which the
+    correction model builds on) and the network + expansion."""
+    from hbinputs.problems import c4_stenosed, c4_stenosis_params
+    from paper_2411_14315_amd import learned
+    kw = dict(n_rings=3, n_z=24, period=10.41)
+    th = c4_stenosis_params(n_train, 2024, K=K, max_severity=0.5)
+    tt = c4_stenosis_params(n_test, 2025, K=K, max_severity=0.5)
+    Y, Y0, st = learned.generate_snapshots([c4_stenosed(x, K=K, **kw) for x in th], batch=128)
+    log(f"learned: generated {n_train} solutions in {st['wall_s']:.1f} s")
+    rank = min(64, n_train // 2)
+    model = learned.WarmStart(rank=rank, hidden=(256, 256)).fit(th, Y, Y0, steps=4000, lr=2e-3)
+    log(f"learned: fit in {model.fit_s:.1f} s, loss {model.losses[0]:.3g} -> {model.losses[-1]:.3g}")
+    rows = []
+    for x in tt:
+        case = learned.Case.build(c4_stenosed(x, K=K, **kw))
+        case.solve(case.plain_start(), 0.0, 1e-8)       # warm caches, untimed
+        rows.append(learned.compare_starts(model, case, x))
+        case.mesh.close()
+
+    def avg(k, f):
+        return float(np.mean([f(r[k]) for r in rows]))
+
+    out = {"workload": "stenosed_pipe_family", "n_nodes": 925, "K": K, "womersley": 4.0,
+           "params": int(th.shape[1]), "n_train": n_train, "n_test": n_test,
+           "pod_rank": model.r, "pod_energy": model.energy,
+           "mlp": [int(th.shape[1]), 256, 256, model.r], "generation_s": st["wall_s"],
+           "fit_s": model.fit_s, "fallbacks": sum(r["learned"]["used"] != "learned" for r in rows),
+           "max_solution_rel_diff": max(r["solution_rel_diff"] for r in rows)}
+    for k in ("plain", "learned"):
+        out[k] = {"newton_iters": avg(k, lambda r: r["newton_iters"]),
+                  "gmres_iters": avg(k, lambda r: r["gmres_iters"]),
+                  "start_s": avg(k, lambda r: r["start_s"]),
+                  "solve_s": avg(k, lambda r: r["wall_s"]),
+                  "total_s": avg(k, lambda r: r["start_s"] + r["wall_s"]),
+                  "start_rel_error": avg(k, lambda r: r["start_err"])}
+    # residual of the start relative to the plain start's, per draw
+    out["learned"]["start_residual_ratio"] = float(np.mean(
+        [r["learned"]["r_start"] / r["plain"]["r_start"] for r in rows]))
+    log(f"learned warm start: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +188,9 @@ def main():
     ap.add_argument("--cfl-max", type=float, default=0.0)
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--no-time-to-solution", action="store_true")
+    ap.add_argument("--learned-train", type=int, default=384,
+                    help="training solutions of the learned warm-start leg (0: skip it)")
+    ap.add_argument("--learned-test", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
@@ -286,6 +336,9 @@ def main():
         if not args.no_time_to_solution:
             out["time_to_1e8"] = {p_: womersley_time_to_solution(hbl, torch, log, p_)
                                   for p_ in res}
+        if args.learned_train > 0:
+            out["learned_warm_start"] = learned_warm_start(torch, log, args.learned_train,
+                                                           args.learned_test)
     out["jv_public"] = {"value": jv_public, "unit": "GDOF-modes/s", "ms": tot,
                         "stages_ms": stages}
     out["jv_public_fp32"] = {"value": dofs / (tot32 * 1e-3) / 1e9, "unit": "GDOF-modes/s",

@@ -124,14 +124,15 @@ def c2_tjunction(K: int = 10, h: float = 3.0 / 70.0, reynolds: float = 500.0,
     return Problem("c2_tjunction", mesh, prm, dirv, np.zeros((nout, prm.N)), R, u_ref=ubar)
 
 
-def c4_stenosis_params(n: int, seed: int, K: int = 10, reynolds: float = 100.0):
+def c4_stenosis_params(n: int, seed: int, K: int = 10, reynolds: float = 100.0,
+                       max_severity: float = 0.7):
     """Parameter draws of the stenosed-pipe family: severity, position and
     the 2K+1 inflow coefficients (23 values for K = 10)."""
     rng = np.random.default_rng(seed)
     ubar = reynolds * MU / (RHO * 2.0)
     qref = ubar * np.pi
     out = np.zeros((n, 2 + 2 * K + 1))
-    out[:, 0] = rng.uniform(0.0, 0.7, n)
+    out[:, 0] = rng.uniform(0.0, max_severity, n)
     out[:, 1] = rng.uniform(2.0, 4.0, n)
     a0 = rng.uniform(0.5, 1.5, n) * qref
     out[:, 2] = a0
@@ -142,9 +143,10 @@ def c4_stenosis_params(n: int, seed: int, K: int = 10, reynolds: float = 100.0):
     return out
 
 
-def c4_stenosed(theta: np.ndarray, K: int = 10, n_rings: int = 12, n_z: int = 90) -> Problem:
+def c4_stenosed(theta: np.ndarray, K: int = 10, n_rings: int = 12, n_z: int = 90,
+                period: float = 1.0) -> Problem:
     mesh = stenosed_pipe_mesh(float(theta[0]), float(theta[1]), n_rings, n_z)
-    prm = Params(period=1.0, K=K)
+    prm = Params(period=period, K=K)
     dirv = poiseuille_dirichlet(mesh, K, [np.asarray(theta[2:], float)])
     return Problem("c4_stenosed_pipe", mesh, prm, dirv,
                    np.zeros((n_outlets(mesh), prm.N)), None, u_ref=float(theta[2]) / np.pi)
@@ -168,3 +170,34 @@ def seeded_state(prob: Problem, seed: int, noise: float = 0.1) -> np.ndarray:
             decay = (1.0 + (j + 1) // 2) ** -1.5
             Y[f, j] = scale * decay * (np.sin(x @ k + ph) + noise * rng.normal(size=m.n_nodes))
     return Y
+
+
+def stack(problems: list[Problem]) -> Problem:
+    """Disjoint union of problems with zero-traction outlets and no
+    resistance: one mesh whose connected components are the given meshes
+    (node blocks in the given order), with one wall, one inlet and one outlet
+    group.  The harmonic-balance equations of disconnected components do not
+    couple, so one solve on the union solves every member."""
+    K = problems[0].params.K
+    if any(p.params != problems[0].params for p in problems):
+        raise ValueError("stacked problems must share their fluid and time parameters")
+    if any(p.outlet_R is not None or np.any(p.outlet_h != 0) for p in problems):
+        raise ValueError("stacking needs zero-traction outlets without resistance")
+    xyz, tets, faces, fgrp, dirv = [], [], [], [], []
+    off = 0
+    for p in problems:
+        m = p.mesh
+        xyz.append(m.xyz)
+        tets.append(m.tets + off)
+        faces.append(m.faces + off)
+        fgrp.append(m.group_kind[m.face_group])
+        dirv.append(p.dirichlet)
+        off += m.n_nodes
+    kinds = np.array([WALL, INLET, OUTLET], np.int32)
+    kind_to_group = {int(k): g for g, k in enumerate(kinds)}
+    grp = np.array([kind_to_group[int(k)] for k in np.concatenate(fgrp)], np.int32)
+    mesh = Mesh(np.concatenate(xyz), np.concatenate(tets).astype(np.int32),
+                np.concatenate(faces).astype(np.int32), grp, kinds,
+                dict(kind="union", sizes=[p.mesh.n_nodes for p in problems]))
+    return Problem("stack", mesh, problems[0].params, np.concatenate(dirv, axis=2),
+                   np.zeros((1, 2 * K + 1)), None, u_ref=max(p.u_ref for p in problems))

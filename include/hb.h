@@ -162,7 +162,10 @@ typedef struct {
   double rtol;       /* stop when ||r||_2 <= rtol * r_ref (default 1e-8)              */
   double r_ref;      /* reference norm; <= 0 means ||r(Y_in)||_2                     */
   double gmres_eta;  /* relative linear tolerance (0.03 in the paper)                 */
-  double cfl;        /* initial pseudo step dt = cfl h_c / u_c                         */
+  double cfl;        /* pseudo step dt = cfl (h_c / u_c) max(r_ref, ||r_0||) / ||r||
+                        (Section 2.3 sets dt ~ h_c / u_c; the growth as the
+                        residual falls is an addition: switched evolution
+                        relaxation)                                               */
   double c1;         /* pseudo-time constant (1.5 for rho_inf = 0)                    */
   int32_t restart;   /* GMRES restart length (default 50)                             */
   int32_t max_newton;
@@ -206,6 +209,49 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
  * run).  Returns HB_ERR_ARG if timing was not enabled for the last call. */
 int hb_set_timing(hb_mesh* mesh, int32_t enable);
 int hb_last_timings(const hb_mesh* mesh, double* ms);
+
+/* ------------------------------------------------------------------------
+ * Learned Newton warm start (a data-driven initial guess, outside the paper's
+ * method: the paper notes HB solutions as a source of training data for
+ * machine-learning models, Section 4).  A multilayer perceptron with BF16
+ * weights and FP32 accumulation maps problem parameters to POD coefficients
+ * of the modal solution; hb_pod_expand forms the guess.  The final FP64
+ * residual of hb_newton_solve decides: callers keep the plain start when the
+ * guess's residual is larger.
+ *
+ * Parameter layout: for each layer l, W_l [out_l][in_l] row-major then
+ * b_l [out_l], as FP32 values (held internally as BF16 plus an FP32 Adam
+ * master copy).  Hidden layers use ReLU, the last is linear.  Loss: mean
+ * squared error (1/(B out)) sum (y - t)^2.  Device arrays are caller-owned;
+ * calls are asynchronous on `stream` except where a host result is returned.
+ * A network handle must not be used by two calls at the same time. */
+typedef struct hb_mlp hb_mlp;
+
+/* widths[0..n_layers]: input width, hidden widths, output width.  params
+ * (host, n_params floats) or NULL for a seeded He-uniform initialisation. */
+int hb_mlp_create(int32_t n_layers, const int32_t* widths, const float* params, uint64_t seed,
+                  hb_mlp** out);
+void hb_mlp_destroy(hb_mlp* net);
+int hb_mlp_num_params(const hb_mlp* net, int64_t* count);
+/* The current (BF16-rounded) parameters as floats, host [n_params]. */
+int hb_mlp_get_params(const hb_mlp* net, float* host_out);
+/* Y (device [B][out]) = net(X) (device [B][in]). */
+int hb_mlp_forward(hb_mlp* net, const float* X, int32_t B, float* Y, void* stream);
+/* Mean squared error against T (device [B][out]) and its gradient with
+ * respect to the parameters: grad device [n_params] (NULL = internal
+ * buffer used by hb_mlp_adam_step); *loss (host, may be NULL) waits for the
+ * result. */
+int hb_mlp_loss_grad(hb_mlp* net, const float* X, const float* T, int32_t B, float* grad,
+                     double* loss, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) with the given
+ * gradient (device, or NULL for the internal one). */
+int hb_mlp_adam_step(hb_mlp* net, const float* grad, float lr, void* stream);
+/* Y[i] = base[i] + mean[i] + sum_k coef[k] basis[k][i], i < L (device
+ * arrays; base [L] double or NULL for none, basis [r][L] double, coef [r]
+ * float; r = 0 allows basis and coef NULL).  Y may alias base.  A model
+ * trained on corrections to the plain start passes that start as base. */
+int hb_pod_expand(int64_t L, int32_t r, const double* base, const double* mean,
+                  const double* basis, const float* coef, double* Y, void* stream);
 
 const char* hb_last_error(void);
 

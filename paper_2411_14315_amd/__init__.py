@@ -76,9 +76,20 @@ def load():
                                     C.POINTER(_Opts), C.POINTER(_Report), vp]
     lib.hb_set_timing.argtypes = [vp, i32]
     lib.hb_last_timings.argtypes = [vp, vp]
+    lib.hb_mlp_create.argtypes = [i32, vp, vp, C.c_uint64, C.POINTER(vp)]
+    lib.hb_mlp_destroy.argtypes = [vp]
+    lib.hb_mlp_destroy.restype = None
+    lib.hb_mlp_num_params.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.hb_mlp_get_params.argtypes = [vp, vp]
+    lib.hb_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+    lib.hb_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, C.POINTER(C.c_double), vp]
+    lib.hb_mlp_adam_step.argtypes = [vp, vp, C.c_float, vp]
+    lib.hb_pod_expand.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp]
     lib.hb_last_error.restype = C.c_char_p
     for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
-                 "hb_newton_solve", "hb_set_timing", "hb_last_timings"):
+                 "hb_newton_solve", "hb_set_timing", "hb_last_timings", "hb_mlp_create",
+                 "hb_mlp_num_params", "hb_mlp_get_params", "hb_mlp_forward", "hb_mlp_loss_grad",
+                 "hb_mlp_adam_step", "hb_pod_expand"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

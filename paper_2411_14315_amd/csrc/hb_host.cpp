@@ -29,6 +29,12 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+void hb::set_last_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
 #define HB_CHECK(...)                                                               \
   do {                                                                              \
     hipError_t e_ = (__VA_ARGS__);                                                  \
@@ -977,7 +983,6 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
     }
   }
   const double dt0 = uc > 0 ? opts->cfl * hc / uc : opts->cfl * hc;
-  double dt = dt0;
   const double dt_max = opts->cfl_max > 0 ? dt0 * opts->cfl_max / opts->cfl : 1e6 * dt0;
 
   DevBuf rbuf;
@@ -990,6 +995,7 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   if (!std::isfinite(rn)) return fail(HB_ERR_NAN, "non-finite initial residual");
   const double ref = opts->r_ref > 0 ? opts->r_ref : rn;
   report->r_ref = ref;
+  const double ser_ref = std::max(ref, rn);
   int status = HB_ERR_NOCONV;
   int it = 0;
   for (;; ++it) {
@@ -998,6 +1004,10 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
       break;
     }
     if (it >= opts->max_newton) break;
+    // switched evolution relaxation: the pseudo step grows as the residual
+    // falls below max(reference, initial residual), so a start whose
+    // residual is already below the reference takes larger steps at once
+    const double dt = std::min(dt0 * ser_ref / std::max(rn, 1e-300), dt_max);
     const double shift = opts->c1 * prm->rho / dt;
     const Phys pj = make_phys(prm, shift);
     const int nc = S.binv ? 4 : 2;
@@ -1020,7 +1030,6 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
       report->newton_iters = it + 1;
       return fail(HB_ERR_NAN, "non-finite residual");
     }
-    dt = std::min(dt * rn / std::max(rn_new, 1e-300), dt_max);
     rn = rn_new;
     if (opts->verbose)
       std::fprintf(stderr, "hb newton %d: |r| = %.3e  gmres %d  dt %.3e\n", it + 1, rn, gi, dt);

@@ -5,8 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace hb {
+
+// Thread-local message returned by hb_last_error().
+void set_last_error(const std::string& msg);
 
 // Library-owned device view of a mesh (structure of arrays).
 struct DevMesh {

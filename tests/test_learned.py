@@ -1,0 +1,248 @@
+"""Learned warm start: the FP64 reference MLP pinned by finite differences
+and invariants (CPU); the HIP forward, backward, Adam and POD-expansion
+kernels against it (GPU); the stacking of problems for batched data
+generation pinned with the oracle residual (CPU); and the gain of the
+trained model over the plain steady start on held-out draws (GPU)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+
+WIDTHS = [23, 256, 256, 64]   # 23 parameters -> 64 POD coefficients
+
+
+def _rand_params(widths, rng, scale=1.0):
+    n = sum(widths[l] * widths[l + 1] + widths[l + 1] for l in range(len(widths) - 1))
+    return rng.normal(0.0, scale, n) / np.sqrt(max(widths))
+
+
+def test_oracle_mlp_gradient_by_finite_differences():
+    rng = np.random.default_rng(0)
+    widths = [5, 7, 6, 3]
+    p = _rand_params(widths, rng, 3.0)
+    X, T = rng.normal(size=(9, 5)), rng.normal(size=(9, 3))
+    _, g = omlp.loss_grad(p, widths, X, T)
+    h = 1e-6
+    fd = np.zeros_like(p)
+    for i in range(p.size):
+        e = np.zeros_like(p)
+        e[i] = h
+        fd[i] = (omlp.loss_grad(p + e, widths, X, T)[0] - omlp.loss_grad(p - e, widths, X, T)[0]) / (2 * h)
+    assert np.linalg.norm(g - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+def test_oracle_mlp_invariants():
+    rng = np.random.default_rng(1)
+    widths = [4, 6, 2]
+    p = _rand_params(widths, rng)
+    X = rng.normal(size=(5, 4))
+    y, _ = omlp.forward(p, widths, X)
+    loss, g = omlp.loss_grad(p, widths, X, y)
+    assert loss == 0.0 and np.all(g == 0.0)            # at the target: zero loss and gradient
+    # a single linear layer is least squares: loss = |X W^T + b - T|^2 / (B out)
+    W = rng.normal(size=(3, 4))
+    b = rng.normal(size=3)
+    T = rng.normal(size=(5, 3))
+    p1 = np.concatenate([W.ravel(), b])
+    l1, _ = omlp.loss_grad(p1, [4, 3], X, T)
+    assert abs(l1 - np.mean((X @ W.T + b - T) ** 2)) <= 1e-14 * l1
+    # a ReLU layer with positive pre-activations composes linearly
+    W1, W2 = np.abs(rng.normal(size=(6, 4))), rng.normal(size=(2, 6))
+    Xp = np.abs(X)
+    p2 = np.concatenate([W1.ravel(), np.ones(6), W2.ravel(), np.zeros(2)])
+    y2, _ = omlp.forward(p2, [4, 6, 2], Xp)
+    assert np.allclose(y2, (Xp @ W1.T + 1.0) @ W2.T, rtol=1e-14)
+
+
+def test_stacked_problem_residual_is_the_concatenation():
+    """A disjoint union of problems (used for batched data generation) has
+    the residual of each member on its own node block."""
+    from hbinputs.problems import c4_stenosed, c4_stenosis_params, seeded_state, stack
+    from oracle import api, fem
+    th = c4_stenosis_params(2, 3, K=1, max_severity=0.5)
+    ps = [c4_stenosed(t, K=1, n_rings=2, n_z=6, period=10.41) for t in th]
+    u = stack(ps)
+    Ys = [seeded_state(p, 20 + i) for i, p in enumerate(ps)]
+    ru = api.residual_modal(fem.from_mesh(u.mesh), u.params, np.concatenate(Ys, axis=2),
+                            u.dirichlet, u.outlet_h, None)
+    off = 0
+    for p, Y in zip(ps, Ys):
+        r = api.residual_modal(fem.from_mesh(p.mesh), p.params, Y, p.dirichlet, p.outlet_h, None)
+        n = p.mesh.n_nodes
+        assert np.linalg.norm(ru[:, :, off:off + n] - r) <= 1e-12 * np.linalg.norm(r)
+        off += n
+
+
+# ------------------------------------------------------------------ GPU
+
+def _bf16(x):
+    """Round FP32 to the nearest BF16 (ties to even), returned as FP32."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    return torch
+
+
+def _net_and_data(torch, B=64, seed=0):
+    from paper_2411_14315_amd.learned import MLP
+    rng = np.random.default_rng(seed)
+    net = MLP(WIDTHS, seed=seed)
+    X = rng.normal(size=(B, WIDTHS[0])).astype(np.float32)
+    T = rng.normal(size=(B, WIDTHS[-1])).astype(np.float32)
+    return net, X, T
+
+
+# Tolerance 1e-5: FP32 accumulation over at most 256 products per output (or
+# 64 batch rows per weight gradient) of BF16 weights and FP32 activations,
+# against FP64 arithmetic on the same BF16-rounded weights; the worst case
+# is sqrt(256) * 2^-24 times the cancellation of the sums (order 10) ~ 1e-5.
+TOL_MLP = 1e-5
+
+
+@pytest.mark.gpu
+def test_mlp_forward_parity(torch_gpu):
+    torch = torch_gpu
+    net, X, _ = _net_and_data(torch)
+    p = net.params()
+    assert np.array_equal(p, _bf16(p))                 # kernels run on BF16 weights
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref, _ = omlp.forward(p.astype(np.float64), WIDTHS, X)
+    assert np.linalg.norm(y - ref) <= TOL_MLP * np.linalg.norm(ref)
+
+
+@pytest.mark.gpu
+def test_mlp_gradient_parity(torch_gpu):
+    torch = torch_gpu
+    net, X, T = _net_and_data(torch, seed=1)
+    p = net.params().astype(np.float64)
+    g = torch.zeros(net.n_params, dtype=torch.float32, device="cuda")
+    loss = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), grad=g)
+    lref, gref = omlp.loss_grad(p, WIDTHS, X, T)
+    assert abs(loss - lref) <= TOL_MLP * lref
+    gg = g.cpu().numpy()
+    assert np.linalg.norm(gg - gref) <= TOL_MLP * np.linalg.norm(gref)
+    # every layer's block, not just the total
+    o = 0
+    for l in range(len(WIDTHS) - 1):
+        k = WIDTHS[l] * WIDTHS[l + 1] + WIDTHS[l + 1]
+        blk = slice(o, o + k)
+        assert np.linalg.norm(gg[blk] - gref[blk]) <= TOL_MLP * np.linalg.norm(gref[blk])
+        o += k
+
+
+@pytest.mark.gpu
+def test_mlp_adam_step(torch_gpu):
+    """One Adam step from given weights: the first bias-corrected step moves
+    each weight by lr g / (|g| + eps) before BF16 rounding."""
+    torch = torch_gpu
+    from paper_2411_14315_amd.learned import MLP
+    rng = np.random.default_rng(2)
+    w0 = _bf16(_rand_params(WIDTHS, rng).astype(np.float32))
+    net = MLP(WIDTHS, params=w0)
+    assert np.array_equal(net.params(), w0)
+    X = torch.from_numpy(rng.normal(size=(32, 23)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.normal(size=(32, 64)).astype(np.float32)).cuda()
+    g = torch.zeros(net.n_params, dtype=torch.float32, device="cuda")
+    net.loss_grad(X, T, grad=g)
+    lr = 1e-2
+    net.adam_step(lr, grad=g)
+    gh = g.cpu().numpy().astype(np.float64)
+    expect = w0.astype(np.float64) - lr * gh / (np.abs(gh) + 1e-8)
+    got = net.params().astype(np.float64)
+    # BF16 keeps 8 significant bits: within one BF16 unit of the exact step
+    assert np.all(np.abs(got - expect) <= 2.0 ** -8 * np.abs(expect) + 1e-7)
+
+
+@pytest.mark.gpu
+def test_mlp_training_reduces_loss(torch_gpu):
+    torch = torch_gpu
+    from paper_2411_14315_amd.learned import MLP
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(256, 4))
+    T = np.stack([np.sin(X[:, 0]) + X[:, 1] * X[:, 2], np.cos(X[:, 3])], axis=1)
+    net = MLP([4, 64, 64, 2], seed=3)
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    Td = torch.from_numpy(T.astype(np.float32)).cuda()
+    first = net.loss_grad(Xd, Td)
+    for _ in range(400):
+        net.loss_grad(Xd, Td, want_loss=False)
+        net.adam_step(3e-3)
+    last = net.loss_grad(Xd, Td)
+    assert last < 0.1 * first
+    ref, _ = omlp.loss_grad(net.params().astype(np.float64), [4, 64, 64, 2], X.astype(np.float32), T.astype(np.float32))
+    assert abs(last - ref) <= TOL_MLP * ref
+
+
+@pytest.mark.gpu
+def test_pod_expand_parity(torch_gpu):
+    torch = torch_gpu
+    from paper_2411_14315_amd.learned import pod_expand
+    rng = np.random.default_rng(4)
+    L, r = 10007, 13
+    mean, basis = rng.normal(size=L), rng.normal(size=(r, L))
+    coef = rng.normal(size=r).astype(np.float32)
+    Y = torch.empty(L, dtype=torch.float64, device="cuda")
+    pod_expand(torch.from_numpy(mean).cuda(), torch.from_numpy(basis).cuda(),
+               torch.from_numpy(coef).cuda(), Y)
+    ref = mean + coef.astype(np.float64) @ basis
+    assert np.linalg.norm(Y.cpu().numpy() - ref) <= 1e-14 * np.linalg.norm(ref)
+    pod_expand(torch.from_numpy(mean).cuda(), None, None, Y)   # rank 0: the mean
+    assert np.array_equal(Y.cpu().numpy(), mean)
+    base = rng.normal(size=L)
+    B = torch.from_numpy(base).cuda()
+    pod_expand(torch.from_numpy(mean).cuda(), torch.from_numpy(basis).cuda(),
+               torch.from_numpy(coef).cuda(), B, base=B)       # in place on the base
+    assert np.linalg.norm(B.cpu().numpy() - base - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+@pytest.mark.gpu
+def test_mlp_error_paths(torch_gpu):
+    import paper_2411_14315_amd as hbl
+    from paper_2411_14315_amd.learned import MLP
+    with pytest.raises(hbl.HBError):
+        MLP([4, 0, 2])
+    with pytest.raises(hbl.HBError):
+        MLP([2, 2], params=np.array([1.0, np.nan, 0.0, 0.0, 0.0, 0.0], np.float32))
+
+
+@pytest.mark.gpu
+def test_learned_warm_start_gain(torch_gpu):
+    """Stenosed-pipe family (925 nodes, K = 2, Womersley number 4): a model
+    trained on 384 solutions the solver generates (as corrections to the
+    plain steady start) gives held-out starts closer to the root than the
+    plain start, and Newton from them reaches the same root in fewer Newton
+    steps in total; the plain start is the fallback."""
+    from hbinputs.problems import c4_stenosed, c4_stenosis_params
+    from paper_2411_14315_amd import learned
+    K, kw = 2, dict(n_rings=3, n_z=24, period=10.41)
+    th_train = c4_stenosis_params(384, 2024, K=K, max_severity=0.5)
+    th_test = c4_stenosis_params(6, 2025, K=K, max_severity=0.5)
+    Y, Y0, st = learned.generate_snapshots([c4_stenosed(t, K=K, **kw) for t in th_train],
+                                           batch=128)
+    assert st["unconverged"] == 0 and Y.shape == Y0.shape == (384, 4 * (2 * K + 1) * 925)
+    model = learned.WarmStart(rank=32, hidden=(128, 128), seed=0).fit(th_train, Y, Y0,
+                                                                      steps=5000, lr=2e-3)
+    assert model.losses[-1] < 0.01 * model.losses[0]
+    newton = {"plain": 0, "learned": 0}
+    err = {"plain": [], "learned": []}
+    for t in th_test:
+        case = learned.Case.build(c4_stenosed(t, K=K, **kw))
+        res = learned.compare_starts(model, case, t)
+        p, l = res["plain"], res["learned"]
+        print(t[:2], "newton", p["newton_iters"], l["newton_iters"], "gmres", p["gmres_iters"],
+              l["gmres_iters"], "start error", p["start_err"], l["start_err"], l["used"],
+              flush=True)
+        assert p["status"] == 0 and l["status"] == 0
+        assert res["solution_rel_diff"] <= 1e-5
+        for k, r in (("plain", p), ("learned", l)):
+            newton[k] += r["newton_iters"]
+            err[k].append(r["start_err"])
+    better = sum(a < b for a, b in zip(err["learned"], err["plain"]))
+    assert np.mean(err["learned"]) < 0.8 * np.mean(err["plain"])
+    assert better >= 4
+    assert newton["learned"] < newton["plain"]
