@@ -196,7 +196,10 @@ typedef struct {
  * classical Gram-Schmidt run twice.  Y (device [4][N][n]) holds the initial
  * guess on entry and the solution on return.  Returns HB_OK on convergence,
  * HB_ERR_NOCONV with Y = last iterate otherwise; the report is filled in both
- * cases. */
+ * cases.  The Krylov basis ((restart + 1) x 4 N n values) and the other solver
+ * buffers are allocated on first use and kept with the mesh for later calls
+ * (counted in hb_mesh_info's device bytes); calls on one mesh must not
+ * overlap. */
 int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
                     const hb_solve_opts* opts, hb_solve_report* report, void* stream);
 

@@ -76,6 +76,23 @@ struct Workspace {
 
 }  // namespace
 
+// Krylov buffers kept on the mesh between solves, pinned host slots for the
+// Arnoldi coefficients, and events.
+struct SolverBufs {
+  DevBuf basis, xvec, rvec, tmp, partial, hdev, rbuf, uc;
+  double* hpin = nullptr;  // pinned host copies of each Arnoldi step's coefficients
+  size_t hpin_n = 0;
+  hipEvent_t evh[2] = {};  // Arnoldi step completion (ping-pong)
+  hipEvent_t evj[4] = {};  // Jv timing: two (start, end) pairs
+  ~SolverBufs() {
+    if (hpin) (void)hipHostFree(hpin);
+    for (auto& e : evh)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : evj)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 struct BlockMap {
   hb::ElemBlocks eb;
   DevBuf ptr, nodes, slot;
@@ -87,9 +104,11 @@ struct hb_mesh {
   DevBuf tets, geo, dmask, of, ofn, oid, mass;
   int64_t n_dirichlet = 0, n_reoriented = 0, n_inlet = 0;
   std::vector<int32_t> inlet_nodes;  // inlet nodes that are not wall nodes
+  DevBuf inlet_dev;                  // the same list on the device
   double mean_vol = 0.0;
   int device = 0;
   Workspace ws;
+  SolverBufs sb;
   // stage timing (hb_set_timing)
   bool timing = false;
   bool timed_call = false;
@@ -99,12 +118,14 @@ struct hb_mesh {
       if (e) (void)hipEventDestroy(e);
   }
   size_t bytes_held() const {
-    return tets.bytes + geo.bytes + dmask.bytes + of.bytes + ofn.bytes + oid.bytes + ws.Sy.bytes +
-           ws.Sv.bytes + ws.acc.bytes + ws.tab.bytes + ws.small.bytes + ws.dg.bytes +
-           ws.dinv.bytes + ws.binv.bytes + ws.Sy32.bytes + ws.Sv32.bytes + ws.acc32.bytes + mass.bytes + bmaps[0].ptr.bytes + bmaps[0].nodes.bytes +
-           bmaps[0].slot.bytes + bmaps[1].ptr.bytes + bmaps[1].nodes.bytes + bmaps[1].slot.bytes +
-           bmaps[2].ptr.bytes + bmaps[2].nodes.bytes + bmaps[2].slot.bytes + bmaps[3].ptr.bytes +
-           bmaps[3].nodes.bytes + bmaps[3].slot.bytes;
+    size_t b = 0;
+    for (const DevBuf* d : {&tets, &geo, &dmask, &of, &ofn, &oid, &mass, &inlet_dev, &ws.Sy, &ws.Sv,
+                            &ws.acc, &ws.tab, &ws.small, &ws.dg, &ws.dinv, &ws.binv, &ws.Sy32,
+                            &ws.Sv32, &ws.acc32, &sb.basis, &sb.xvec, &sb.rvec, &sb.tmp,
+                            &sb.partial, &sb.hdev, &sb.rbuf, &sb.uc})
+      b += d->bytes;
+    for (const auto& bm : bmaps) b += bm.ptr.bytes + bm.nodes.bytes + bm.slot.bytes;
+    return b;
   }
 };
 
@@ -532,6 +553,11 @@ int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int
     m->n_inlet += inlet[a];
     if (inlet[a] && !wall[a]) m->inlet_nodes.push_back((int32_t)a);
   }
+  if (!m->inlet_nodes.empty()) {
+    HB_CHECK(m->inlet_dev.ensure(sizeof(int32_t) * m->inlet_nodes.size()));
+    HB_CHECK(hipMemcpy(m->inlet_dev.p, m->inlet_nodes.data(),
+                       sizeof(int32_t) * m->inlet_nodes.size(), hipMemcpyHostToDevice));
+  }
   m->n_reoriented = reoriented;
   m->mean_vol = vsum / ne;
   *out = m.release();
@@ -711,18 +737,12 @@ struct Solver {
   int nblk;
   int jv_kind;
   const double* binv = nullptr;  // per-node time blocks, or NULL for the diagonal
-  DevBuf basis, xvec, rvec, tmp, partial, hdev;
-  std::vector<double> hhost;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  SolverBufs* sb = nullptr;
   double jv_ms = 0.0;
   int n_jv = 0;
+  bool jv_pending[2] = {false, false};
 
-  ~Solver() {
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-  }
-
-  T* Q(int j) { return basis.as<T>() + (size_t)j * L; }
+  T* Q(int j) { return sb->basis.as<T>() + (size_t)j * L; }
   // the state as seen by the Krylov operator
   const T* state() {
     if constexpr (std::is_same<T, double>::value) return m->ws.Sy.as<double>();
@@ -738,14 +758,25 @@ struct Solver {
   }
 
   int alloc() {
-    HB_CHECK(basis.ensure(sizeof(T) * (size_t)(restart + 1) * L));
-    HB_CHECK(xvec.ensure(sizeof(T) * L));
-    HB_CHECK(rvec.ensure(sizeof(T) * L));
-    HB_CHECK(tmp.ensure(sizeof(T) * L));
-    HB_CHECK(partial.ensure(sizeof(double) * (size_t)(restart + 2) * nblk));
-    HB_CHECK(hdev.ensure(sizeof(double) * (4 * (size_t)(restart + 1) + 8)));
-    HB_CHECK(hipEventCreate(&ev0));
-    HB_CHECK(hipEventCreate(&ev1));
+    sb = &m->sb;
+    HB_CHECK(sb->basis.ensure(sizeof(T) * (size_t)(restart + 1) * L));
+    HB_CHECK(sb->xvec.ensure(sizeof(T) * L));
+    HB_CHECK(sb->rvec.ensure(sizeof(T) * L));
+    HB_CHECK(sb->tmp.ensure(sizeof(T) * L));
+    HB_CHECK(sb->partial.ensure(sizeof(double) * (size_t)(restart + 2) * nblk));
+    HB_CHECK(sb->hdev.ensure(sizeof(double) * (4 * (size_t)(restart + 1) + 8)));
+    const size_t slot = 2 * (size_t)(restart + 1) + 1;
+    if (sb->hpin_n < slot * restart) {
+      if (sb->hpin) HB_CHECK(hipHostFree(sb->hpin));
+      sb->hpin = nullptr;
+      sb->hpin_n = 0;
+      HB_CHECK(hipHostMalloc((void**)&sb->hpin, sizeof(double) * slot * restart));
+      sb->hpin_n = slot * restart;
+    }
+    for (auto& e : sb->evh)
+      if (!e) HB_CHECK(hipEventCreate(&e));
+    for (auto& e : sb->evj)
+      if (!e) HB_CHECK(hipEventCreate(&e));
     if constexpr (!std::is_same<T, double>::value) {
       int rc = ensure_f32(m);
       if (rc) return rc;
@@ -782,9 +813,9 @@ struct Solver {
 
   template <typename V>
   int norm(const V* x, double& out) {
-    HB_CHECK(hb::vec_dots<V>(x, L, 1, x, L, partial.as<double>(), nblk, hdev.as<double>(), st));
+    HB_CHECK(hb::vec_dots<V>(x, L, 1, x, L, sb->partial.as<double>(), nblk, sb->hdev.as<double>(), st));
     double v = 0.0;
-    HB_CHECK(hipMemcpyAsync(&v, hdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HB_CHECK(hipMemcpyAsync(&v, sb->hdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
     HB_CHECK(hipStreamSynchronize(st));
     out = std::sqrt(v);
     return HB_OK;
@@ -798,7 +829,12 @@ struct Solver {
     const Phys p = make_phys(prm, shift);
     T* Sv = dir();
     T* acc = accum();
-    HB_CHECK(hipEventRecord(ev0, st));
+    const int pr = n_jv & 1;
+    if (jv_pending[pr]) {
+      int rc = collect_jv(pr);
+      if (rc) return rc;
+    }
+    HB_CHECK(hipEventRecord(sb->evj[2 * pr], st));
     HB_CHECK(hb::prepare_direction<T, T>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab, Sv,
                                          acc, s.dQ, m->dm.n_out * N, st));
     if (jv_kind == HB_JV_EXACT) {
@@ -815,19 +851,41 @@ struct Solver {
         return fail(HB_ERR_ARG, "the paper tangent is available in FP64 only");
       }
     }
-    HB_CHECK(hipEventRecord(ev1, st));
-    HB_CHECK(hipEventSynchronize(ev1));
-    float ms = 0.f;
-    HB_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-    jv_ms += ms;
+    HB_CHECK(hipEventRecord(sb->evj[2 * pr + 1], st));
+    jv_pending[pr] = true;
     ++n_jv;
     return HB_OK;
   }
 
+  // Adds the duration of a recorded Jv (waits for it).
+  int collect_jv(int pr) {
+    HB_CHECK(hipEventSynchronize(sb->evj[2 * pr + 1]));
+    float ms = 0.f;
+    HB_CHECK(hipEventElapsedTime(&ms, sb->evj[2 * pr], sb->evj[2 * pr + 1]));
+    jv_ms += ms;
+    jv_pending[pr] = false;
+    return HB_OK;
+  }
+  int collect_all_jv() {
+    for (int pr = 0; pr < 2; ++pr)
+      if (jv_pending[pr]) {
+        int rc = collect_jv(pr);
+        if (rc) return rc;
+      }
+    return HB_OK;
+  }
+
   // Right-preconditioned restarted GMRES on (J M^-1) x = -r; CGS2.
+  //
+  // The Arnoldi steps run on the device without host round trips: the
+  // Gram-Schmidt coefficients stay on the device, the new basis vector is
+  // normalised there, and the coefficients are copied to pinned host slots.
+  // The host reads step j's coefficients (Givens rotations, convergence
+  // test) while step j+1 is already queued, so the GPU never waits for the
+  // host; a converged cycle has computed one step more than it uses.
   int gmres(const double* r, double shift, double eta, int max_it, int& iters) {
-    T* x = xvec.as<T>();
-    T* rl = rvec.as<T>();
+    T* x = sb->xvec.as<T>();
+    T* rl = sb->rvec.as<T>();
     HB_CHECK(hb::vec_zero<T>(x, L, st));
     HB_CHECK((hb::vec_copy_scaled<T, double>(rl, r, L, -1.0, st)));
     double beta;
@@ -837,36 +895,44 @@ struct Solver {
     if (beta == 0.0) return HB_OK;
     const double target = eta * beta;
     const int mr = restart;
+    const size_t slot = 2 * (size_t)(mr + 1) + 1;
     std::vector<double> Hm((size_t)(mr + 1) * mr), cs(mr), sn(mr), g(mr + 1), yv(mr);
-    hhost.assign(2 * (mr + 1) + 1, 0.0);
     double bc = beta;
+    double* h1 = sb->hdev.as<double>();
+    double* h2 = h1 + (mr + 1);
+    double* h3 = h2 + (mr + 1);
+    double* ydev = h1 + slot;
+    // queue Arnoldi step j: w = A v_j, two Gram-Schmidt passes, |w|^2, normalise
+    auto enqueue = [&](int j) -> int {
+      T* wj = Q(j + 1);
+      int rc2 = apply(Q(j), wj, shift);
+      if (rc2) return rc2;
+      HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, sb->partial.as<double>(), nblk, h1, st));
+      HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h1, -1.0, L, st));
+      HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, sb->partial.as<double>(), nblk, h2, st));
+      HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h2, -1.0, L, st));
+      HB_CHECK(hb::vec_dots<T>(wj, L, 1, wj, L, sb->partial.as<double>(), nblk, h3, st));
+      HB_CHECK(hb::vec_scale_inv_norm<T>(wj, L, h3, st));
+      HB_CHECK(hipMemcpyAsync(sb->hpin + (size_t)j * slot, h1, sizeof(double) * slot,
+                              hipMemcpyDeviceToHost, st));
+      HB_CHECK(hipEventRecord(sb->evh[j & 1], st));
+      return HB_OK;
+    };
     while (true) {
       HB_CHECK((hb::vec_copy_scaled<T, T>(Q(0), rl, L, 1.0 / bc, st)));
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = bc;
       int jend = 0;
       bool done = false;
-      for (int j = 0; j < mr; ++j) {
-        T* wj = Q(j + 1);
-        rc = apply(Q(j), wj, shift);
-        if (rc) return rc;
-        double* h1 = hdev.as<double>();
-        double* h2 = h1 + (mr + 1);
-        double* h3 = h2 + (mr + 1);
-        HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h1, st));
-        HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h1, -1.0, L, st));
-        HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, partial.as<double>(), nblk, h2, st));
-        HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h2, -1.0, L, st));
-        HB_CHECK(hb::vec_dots<T>(wj, L, 1, wj, L, partial.as<double>(), nblk, h3, st));
-        HB_CHECK(hipMemcpyAsync(hhost.data(), h1, sizeof(double) * (2 * (mr + 1) + 1),
-                                hipMemcpyDeviceToHost, st));
-        HB_CHECK(hipStreamSynchronize(st));
+      // host side of step j: Hessenberg column, Givens rotation, test
+      auto finish = [&](int j) -> int {
+        HB_CHECK(hipEventSynchronize(sb->evh[j & 1]));
+        const double* hh = sb->hpin + (size_t)j * slot;
         double* col = &Hm[(size_t)j * (mr + 1)];
-        for (int k = 0; k <= j; ++k) col[k] = hhost[k] + hhost[(mr + 1) + k];
-        const double hn = std::sqrt(std::max(hhost[2 * (mr + 1)], 0.0));
-        col[j + 1] = hn;
+        for (int k = 0; k <= j; ++k) col[k] = hh[k] + hh[(mr + 1) + k];
+        const double hn = std::sqrt(std::max(hh[2 * (mr + 1)], 0.0));
         if (!std::isfinite(hn)) return fail(HB_ERR_NAN, "non-finite Krylov vector");
-        if (hn > 0) HB_CHECK(hb::vec_scale<T>(wj, L, 1.0 / hn, st));
+        col[j + 1] = hn;
         for (int k = 0; k < j; ++k) {
           const double a = col[k], b = col[k + 1];
           col[k] = cs[k] * a + sn[k] * b;
@@ -881,9 +947,21 @@ struct Solver {
         g[j] = cs[j] * g[j];
         ++iters;
         jend = j + 1;
-        if (std::fabs(g[j + 1]) <= target || iters >= max_it || hn == 0.0) {
-          done = true;
-          break;
+        if (std::fabs(g[j + 1]) <= target || iters >= max_it || hn == 0.0) done = true;
+        return HB_OK;
+      };
+      for (int j = 0; j < mr && !done; ++j) {
+        if (iters + j - jend < max_it) {  // queue step j unless the budget is spent
+          rc = enqueue(j);
+          if (rc) return rc;
+        }
+        if (j > 0) {
+          rc = finish(j - 1);
+          if (rc) return rc;
+        }
+        if (!done && j == mr - 1) {
+          rc = finish(j);
+          if (rc) return rc;
         }
       }
       for (int i = jend - 1; i >= 0; --i) {
@@ -892,23 +970,22 @@ struct Solver {
         const double d = Hm[(size_t)i * (mr + 1) + i];
         yv[i] = d != 0.0 ? v / d : 0.0;
       }
-      double* ydev = hdev.as<double>() + 2 * (mr + 1) + 1;
       HB_CHECK(hipMemcpyAsync(ydev, yv.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
       HB_CHECK(hb::vec_axpy_multi<T>(x, Q(0), L, jend, ydev, 1.0, L, st));
       HB_CHECK(hipStreamSynchronize(st));
       if (done && (std::fabs(g[jend]) <= target || iters >= max_it)) break;
       // restart: rl = -r - (J M^-1) x
-      rc = apply(x, tmp.as<T>(), shift);
+      rc = apply(x, sb->tmp.as<T>(), shift);
       if (rc) return rc;
       HB_CHECK((hb::vec_copy_scaled<T, double>(rl, r, L, -1.0, st)));
       double one = 1.0;
       HB_CHECK(hipMemcpyAsync(ydev, &one, sizeof(double), hipMemcpyHostToDevice, st));
-      HB_CHECK(hb::vec_axpy_multi<T>(rl, tmp.as<T>(), L, 1, ydev, -1.0, L, st));
+      HB_CHECK(hb::vec_axpy_multi<T>(rl, sb->tmp.as<T>(), L, 1, ydev, -1.0, L, st));
       rc = norm<T>(rl, bc);
       if (rc) return rc;
       if (bc <= target || iters >= max_it) break;
     }
-    return HB_OK;
+    return collect_all_jv();
   }
 
   // state += M^-1 x (FP64), skipping Dirichlet velocity entries.
@@ -916,13 +993,13 @@ struct Solver {
     Workspace& w = m->ws;
     const double* tab = w.tab.as<double>();
     if (binv) {
-      HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, xvec.as<T>(), 4, w.dinv.as<double>(),
+      HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, sb->xvec.as<T>(), 4, w.dinv.as<double>(),
                                                  binv, 1, tab, w.Sv.as<double>(), nullptr,
                                                  nullptr, 0, st)));
       HB_CHECK(hb::vec_mul_dinv_add<double>(w.Sy.as<double>(), w.Sv.as<double>(), nullptr,
                                             m->dm.dmask, m->dm.n, N, hb::NCH, hb::NCH, 1.0, st));
     } else {
-      HB_CHECK(hb::vec_mul_dinv_add<T>(w.Sy.as<double>(), xvec.as<T>(), w.dinv.as<double>(),
+      HB_CHECK(hb::vec_mul_dinv_add<T>(w.Sy.as<double>(), sb->xvec.as<T>(), w.dinv.as<double>(),
                                        m->dm.dmask, m->dm.n, N, hb::NCH, 4, 1.0, st));
     }
     return HB_OK;
@@ -962,32 +1039,20 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   const double hc = std::cbrt(6.0 * std::sqrt(2.0) * m->mean_vol);
   double uc = 0.0;
   if (!m->inlet_nodes.empty()) {
-    std::vector<double> dh((size_t)3 * N * m->dm.n);
-    HB_CHECK(hipMemcpyAsync(dh.data(), bc->dirichlet, sizeof(double) * dh.size(),
-                            hipMemcpyDeviceToHost, st));
+    HB_CHECK(m->sb.uc.ensure(sizeof(double) * N));
+    HB_CHECK(hb::inlet_speed(bc->dirichlet, m->dm.n, N, m->inlet_dev.as<int32_t>(),
+                             (int64_t)m->inlet_nodes.size(), tab, m->sb.uc.as<double>(), st));
+    std::vector<double> us(N);
+    HB_CHECK(hipMemcpyAsync(us.data(), m->sb.uc.p, sizeof(double) * N, hipMemcpyDeviceToHost,
+                            st));
     HB_CHECK(hipStreamSynchronize(st));
-    const double* Binv = w.tab_host.data() + hb::TAB_BINV * (size_t)N * N;
-    for (int s = 0; s < N; ++s) {
-      double sum = 0.0;
-      for (int32_t a : m->inlet_nodes) {
-        double g2 = 0.0;
-        for (int i = 0; i < 3; ++i) {
-          double v = 0.0;
-          for (int mm = 0; mm < N; ++mm)
-            v += Binv[s * N + mm] * dh[((size_t)i * N + mm) * m->dm.n + a];
-          g2 += v * v;
-        }
-        sum += std::sqrt(g2);
-      }
-      uc = std::max(uc, sum / (double)m->inlet_nodes.size());
-    }
+    for (double v : us) uc = std::max(uc, v);
   }
   const double dt0 = uc > 0 ? opts->cfl * hc / uc : opts->cfl * hc;
   const double dt_max = opts->cfl_max > 0 ? dt0 * opts->cfl_max / opts->cfl : 1e6 * dt0;
 
-  DevBuf rbuf;
-  HB_CHECK(rbuf.ensure(sizeof(double) * L));
-  double* r = rbuf.as<double>();
+  HB_CHECK(m->sb.rbuf.ensure(sizeof(double) * L));
+  double* r = m->sb.rbuf.as<double>();
   double rn = 0.0;
   rc = S.residual(r, rn);
   if (rc) return rc;

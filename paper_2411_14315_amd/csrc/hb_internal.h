@@ -123,6 +123,12 @@ template <typename TD, typename TS>
 hipError_t vec_copy_scaled(TD* dst, const TS* src, int64_t L, double s, hipStream_t st);
 template <typename T>
 hipError_t vec_zero(T* x, int64_t L, hipStream_t st);
+// x /= sqrt(*nrm2) (device scalar) when positive and finite
+template <typename T>
+hipError_t vec_scale_inv_norm(T* x, int64_t L, const double* nrm2, hipStream_t st);
+// out[s] = mean |u(t_s)| over the given inlet nodes of the modal Dirichlet data
+hipError_t inlet_speed(const double* d, int64_t n, int N, const int32_t* nodes, int64_t ni,
+                       const double* tab, double* out, hipStream_t st);
 template <typename TU>
 hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const uint8_t* dmask,
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st);

@@ -275,64 +275,87 @@ k_prepare(int64_t n, int N, const TQ* q, int in_ch, const double* __restrict__ d
 // function's -H N_A against tau L, with L's rho H u and rho u.grad u, and
 // the streamline test against tau rho H u), inverted by Gauss-Jordan
 // elimination without pivoting (the symmetric part of B is diag(K_AA) +
-// rho H^T diag(T_AA) H, positive).  One wavefront per node with the N x N
-// block in LDS; lane j owns column j.  Within a wavefront the
-// LDS accesses of one pivot step are ordered by program order, so no
-// barrier is needed between pivots.  Requires N <= 64 (one column per
-// lane).  Identity at Dirichlet nodes (and for the idle wavefront of a
-// ragged last workgroup).  dg has 4 channels (K, L, T, X).
-constexpr int FACT_WAVES = 2;
-__global__ void __launch_bounds__(64 * FACT_WAVES)
-k_block_factor(int64_t n, int N, const double* __restrict__ dg, const double* __restrict__ mass,
-               double rho, const double* __restrict__ tab, const uint8_t* __restrict__ dmask,
-               double* __restrict__ binv) {
+// rho H^T diag(T_AA) H, positive).
+//
+// One wavefront per workgroup handles P = floor(64 / N) consecutive nodes
+// (3 at N = 21), each block in LDS.  Building B spreads the P N^2 entries
+// over all lanes; in the elimination lane (q, j) owns column j of node q's
+// block.  Within a wavefront, LDS accesses are ordered by program order, so
+// the elimination needs no barrier: in every row chunk all lanes read the
+// pivot column before the pivot column's owner writes it.  Requires
+// N <= 64.  Identity at Dirichlet nodes.  dg has 4 channels (K, L, T, X),
+// node-major, so the P nodes' rows are one contiguous range.
+constexpr int FACT_CHUNK = 4;
+__global__ void __launch_bounds__(64)
+k_block_factor(int64_t n, int N, int P, const double* __restrict__ dg,
+               const double* __restrict__ mass, double rho, const double* __restrict__ tab,
+               const uint8_t* __restrict__ dmask, double* __restrict__ binv) {
   extern __shared__ double sm[];
   const int NN = N * N;
-  double* sH = sm;
-  for (int i = threadIdx.x; i < NN; i += 64 * FACT_WAVES) sH[i] = tab[TAB_H * NN + i];
+  double* sH = sm;                  // [N][N]
+  double* sD = sH + NN;             // [P][4][N]  K, L, T, X
+  double* sB = sD + P * 4 * N;      // [P][N][N]
+  const int lane = threadIdx.x;
+  const int64_t a0 = (int64_t)blockIdx.x * P;
+  const int np = (int)min<int64_t>(P, n - a0);
+  for (int i = lane; i < NN; i += 64) sH[i] = tab[TAB_H * NN + i];
+  const double* src = dg + a0 * 4 * N;
+  for (int i = lane; i < np * 4 * N; i += 64) sD[i] = src[i];
   __syncthreads();
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* B = sm + NN * (1 + wv);
-  const int64_t a = (int64_t)blockIdx.x * FACT_WAVES + wv;
-  const bool valid = a < n;
-  const bool ident = !valid || dmask[a] != 0;
-  const double* Kd = dg + (valid ? a : 0) * 4 * N;
-  const double* Td = Kd + 2 * N;
-  const double* Xd = Kd + 3 * N;
-  const double cm = valid ? rho * mass[a] : 0.0;
-  const int j = lane;
-  if (j < N)
-    for (int s = 0; s < N; ++s) {
-      double v;
-      if (ident) {
-        v = (s == j) ? 1.0 : 0.0;
-      } else {
-        v = (cm + Xd[s]) * sH[s * N + j] - sH[s * N + j] * Xd[j];
-        double h2 = 0.0;
-        for (int t = 0; t < N; ++t) h2 += sH[s * N + t] * Td[t] * sH[t * N + j];
-        v -= rho * h2;
-        if (s == j) v += Kd[s];
-      }
-      B[s * N + j] = v;
+
+  // B entries, e = (q, s, j)
+  for (int e = lane; e < np * NN; e += 64) {
+    const int q = e / NN;
+    const int r = e - q * NN;
+    const int sr = r / N;
+    const int j = r - sr * N;
+    const int64_t a = a0 + q;
+    double v;
+    if (dmask[a]) {
+      v = (sr == j) ? 1.0 : 0.0;
+    } else {
+      const double* Kd = sD + q * 4 * N;
+      const double* Td = Kd + 2 * N;
+      const double* Xd = Kd + 3 * N;
+      const double hsj = sH[sr * N + j];
+      v = (rho * mass[a] + Xd[sr]) * hsj - hsj * Xd[j];
+      double h2 = 0.0;
+      for (int t = 0; t < N; ++t) h2 += sH[sr * N + t] * Td[t] * sH[t * N + j];
+      v -= rho * h2;
+      if (sr == j) v += Kd[sr];
     }
+    sB[e] = v;
+  }
+  __syncthreads();
+
+  // Gauss-Jordan inversion in place; lane (q, j)
+  const int q = lane / N;
+  const int j = lane - q * N;
+  const bool act = q < np;
+  double* B = sB + (act ? q : 0) * NN;
   for (int kp = 0; kp < N; ++kp) {
-    const double ip = 1.0 / B[kp * N + kp];
-    if (j < N) {
+    if (act) {
+      const double ip = 1.0 / B[kp * N + kp];
       const double rk = (j == kp) ? ip : B[kp * N + j] * ip;
-      for (int i = 0; i < N; ++i) {
-        const double f = B[i * N + kp];
-        double nv;
-        if (i == kp)
-          nv = rk;
-        else
-          nv = (j == kp ? 0.0 : B[i * N + j]) - f * rk;
-        B[i * N + j] = nv;
+      for (int i0 = 0; i0 < N; i0 += FACT_CHUNK) {
+        double f[FACT_CHUNK], b[FACT_CHUNK];
+#pragma unroll
+        for (int c = 0; c < FACT_CHUNK; ++c) {
+          const int i = i0 + c;
+          f[c] = i < N ? B[i * N + kp] : 0.0;
+          b[c] = i < N ? B[i * N + j] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < FACT_CHUNK; ++c) {
+          const int i = i0 + c;
+          if (i < N) B[i * N + j] = (i == kp) ? rk : (j == kp ? 0.0 : b[c]) - f[c] * rk;
+        }
       }
     }
   }
-  if (!valid || j >= N) return;
-  double* out = binv + a * NN;
-  for (int s = 0; s < N; ++s) out[s * N + j] = B[s * N + j];
+  __syncthreads();
+  double* out = binv + a0 * NN;
+  for (int e = lane; e < np * NN; e += 64) out[e] = sB[e];
 }
 
 // Sample-space rows: out[a][i][s] = acc r^m_i - (H z_i) (use_z), out[a][3] =
@@ -1046,6 +1069,50 @@ k_scale(T* __restrict__ x, int64_t L, double s) {
     x[i] = (T)((double)x[i] * s);
 }
 
+// x /= sqrt(*nrm2) when that norm is positive and finite (Arnoldi
+// normalisation without a round trip to the host).
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_scale_inv_norm(T* __restrict__ x, int64_t L, const double* __restrict__ nrm2) {
+  const double nv = sqrt(fmax(*nrm2, 0.0));
+  if (!(nv > 0.0) || !isfinite(nv)) return;
+  const double s = 1.0 / nv;
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride)
+    x[i] = (T)((double)x[i] * s);
+}
+
+// out[s] = mean over the listed inlet nodes of |u(t_s)|, u(t_s) from the
+// modal Dirichlet data d[3][N][n] (the characteristic speed of the CFL rule).
+__global__ void __launch_bounds__(BLK)
+k_inlet_speed(const double* __restrict__ d, int64_t n, int N, const int32_t* __restrict__ nodes,
+              int64_t ni, const double* __restrict__ tab, double* __restrict__ out) {
+  __shared__ double red[BLK / 64];
+  const int s = blockIdx.x;
+  const double* Binv = tab + (size_t)TAB_BINV * N * N + (size_t)s * N;
+  double sum = 0.0;
+  for (int64_t k = threadIdx.x; k < ni; k += BLK) {
+    const int64_t a = nodes[k];
+    double g2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      double v = 0.0;
+      for (int mm = 0; mm < N; ++mm) v += Binv[mm] * d[((int64_t)i * N + mm) * n + a];
+      g2 += v * v;
+    }
+    sum += sqrt(g2);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
+  if (lane == 0) red[wv] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < BLK / 64; ++q) t += red[q];
+    out[s] = t / (double)ni;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_fill(T* __restrict__ x, int64_t L, double v) {
@@ -1132,10 +1199,12 @@ hipError_t prepare_direction(const DevMesh& m, int N, const TQ* q, int in_ch, co
 
 hipError_t block_factor(const DevMesh& m, int N, const double* dg, const double* mass,
                         double rho, const double* tab, double* binv, hipStream_t st) {
-  const size_t lds = sizeof(double) * (size_t)N * N * (1 + FACT_WAVES);
-  const unsigned grid = (unsigned)((m.n + FACT_WAVES - 1) / FACT_WAVES);
-  hipLaunchKernelGGL(k_block_factor, dim3(grid), dim3(64 * FACT_WAVES), lds, st, m.n, N, dg, mass,
-                     rho, tab, m.dmask, binv);
+  if (N < 1 || N > 64) return hipErrorInvalidValue;
+  const int P = 64 / N;
+  const size_t lds = sizeof(double) * ((size_t)N * N * (1 + P) + (size_t)P * 4 * N);
+  const unsigned grid = (unsigned)((m.n + P - 1) / P);
+  hipLaunchKernelGGL(k_block_factor, dim3(grid), dim3(64), lds, st, m.n, N, P, dg, mass, rho, tab,
+                     m.dmask, binv);
   return hipGetLastError();
 }
 
@@ -1248,6 +1317,19 @@ hipError_t vec_copy_scaled(TD* dst, const TS* src, int64_t L, double s, hipStrea
 }
 
 template <typename T>
+hipError_t vec_scale_inv_norm(T* x, int64_t L, const double* nrm2, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_inv_norm<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, nrm2);
+  return hipGetLastError();
+}
+
+hipError_t inlet_speed(const double* d, int64_t n, int N, const int32_t* nodes, int64_t ni,
+                       const double* tab, double* out, hipStream_t st) {
+  if (ni <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inlet_speed, dim3(N), dim3(BLK), 0, st, d, n, N, nodes, ni, tab, out);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t vec_zero(T* x, int64_t L, hipStream_t st) {
   hipLaunchKernelGGL((k_fill<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, x, L, 0.0);
   return hipGetLastError();
@@ -1298,6 +1380,7 @@ HB_INST_IO(float, double)
   template hipError_t vec_axpy_multi<T>(T*, const T*, int64_t, int, const double*, double,     \
                                         int64_t, hipStream_t);                                  \
   template hipError_t vec_scale<T>(T*, int64_t, double, hipStream_t);                           \
+  template hipError_t vec_scale_inv_norm<T>(T*, int64_t, const double*, hipStream_t);           \
   template hipError_t vec_zero<T>(T*, int64_t, hipStream_t);                                    \
   template hipError_t vec_mul_dinv_add<T>(double*, const T*, const double*, const uint8_t*,    \
                                           int64_t, int, int, int, double, hipStream_t);
