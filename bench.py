@@ -48,6 +48,29 @@ HBM_PEAK_GBS = 8000.0
 ELEM_FLOPS = {"exact": 1680, "paper": 970, "residual": 1040}
 
 
+# HBM bytes per launch of the FP64 exact-Jv element kernel at the benchmark
+# size, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) counters,
+# each scale read off a plain 1 GiB device copy; valid while the
+# element-kernel source section hashes to the recorded value.
+ELEM_TRAFFIC = {"sha256_prefix": "5d23b4be6d9aa39b", "fetch_kib": 382066, "write_kib": 1193487,
+                "fetch_scale": 2.0, "write_scale": 1.0, "n_nodes": 158688, "n_tets": 848252,
+                "K": 10, "profile": "profiles/k_elem_jvp_exact_tjunction_K10_traffic.md"}
+
+
+def elem_traffic(n, ne, K):
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2411_14315_amd", "csrc", "hb_kernels.hip")).read()
+    a = src.index("// ------------------------------------------------------------- elements")
+    b = src.index("// --------------------------------------------------------------- faces")
+    t = ELEM_TRAFFIC
+    if (hashlib.sha256(src[a:b].encode()).hexdigest()[:16] != t["sha256_prefix"]
+            or (n, ne, K) != (t["n_nodes"], t["n_tets"], t["K"])):
+        return None, None
+    rd = t["fetch_kib"] * 1024 * t["fetch_scale"]
+    wr = t["write_kib"] * 1024 * t["write_scale"]
+    return rd + wr, {"read_bytes": rd, "write_bytes": wr, "source": t["profile"]}
+
+
 def elem_bytes(n, ne, N, kind):
     """Algorithmic HBM bytes of one element-kernel launch: node samples read
     once (7 channels of state, 7 of direction for Jv), accumulator rows
@@ -283,12 +306,16 @@ def main():
     elem_ms = stages["element"]
     flops = ELEM_FLOPS["exact"] * ne * N
     eb = elem_bytes(n, ne, N, "exact")
+    traffic, traffic_detail = elem_traffic(n, ne, args.K)
     roofline = {"bound": "alu", "achieved": flops / (elem_ms * 1e-3) / 1e12,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": flops / (elem_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                "traffic": None,
+                "traffic": traffic,
                 "kernel": "k_elem_jvp_exact", "kernel_ms": elem_ms,
                 "hbm_algorithmic_GBs": eb / (elem_ms * 1e-3) / 1e9}
+    if traffic is not None:
+        roofline["traffic_detail"] = dict(traffic_detail,
+                                          hbm_measured_GBs=traffic / (elem_ms * 1e-3) / 1e9)
 
     out = {"metric": METRIC, "unit": "GDOF-modes/s", "n_gpus": 1, "higher_is_better": True,
            "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
