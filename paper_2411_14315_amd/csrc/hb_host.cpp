@@ -726,6 +726,9 @@ namespace {
 // the GMRES solution are FP32 while the residual, the preconditioner, the
 // Gram-Schmidt coefficients (FP64 accumulation) and the Newton update stay
 // FP64, so that the outer iteration refines to the FP64 residual.
+// workgroup cap of the fused second Gram-Schmidt update and norm
+constexpr int kNormBlocks = 4096;
+
 template <typename T>
 struct Solver {
   hb_mesh* m;
@@ -763,7 +766,8 @@ struct Solver {
     HB_CHECK(sb->xvec.ensure(sizeof(T) * L));
     HB_CHECK(sb->rvec.ensure(sizeof(T) * L));
     HB_CHECK(sb->tmp.ensure(sizeof(T) * L));
-    HB_CHECK(sb->partial.ensure(sizeof(double) * (size_t)(restart + 2) * nblk));
+    HB_CHECK(sb->partial.ensure(sizeof(double) *
+                                std::max<size_t>((size_t)(restart + 2) * nblk, kNormBlocks)));
     HB_CHECK(sb->hdev.ensure(sizeof(double) * (4 * (size_t)(restart + 1) + 8)));
     const size_t slot = 2 * (size_t)(restart + 1) + 1;
     if (sb->hpin_n < slot * restart) {
@@ -907,11 +911,11 @@ struct Solver {
       T* wj = Q(j + 1);
       int rc2 = apply(Q(j), wj, shift);
       if (rc2) return rc2;
-      HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, sb->partial.as<double>(), nblk, h1, st));
+      double* part = sb->partial.as<double>();
+      HB_CHECK(hb::vec_mdots<T>(Q(0), L, j + 1, wj, L, part, nblk, h1, st));
       HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h1, -1.0, L, st));
-      HB_CHECK(hb::vec_dots<T>(Q(0), L, j + 1, wj, L, sb->partial.as<double>(), nblk, h2, st));
-      HB_CHECK(hb::vec_axpy_multi<T>(wj, Q(0), L, j + 1, h2, -1.0, L, st));
-      HB_CHECK(hb::vec_dots<T>(wj, L, 1, wj, L, sb->partial.as<double>(), nblk, h3, st));
+      HB_CHECK(hb::vec_mdots<T>(Q(0), L, j + 1, wj, L, part, nblk, h2, st));
+      HB_CHECK(hb::vec_axpy_norm<T>(wj, Q(0), L, j + 1, h2, L, part, kNormBlocks, h3, st));
       HB_CHECK(hb::vec_scale_inv_norm<T>(wj, L, h3, st));
       HB_CHECK(hipMemcpyAsync(sb->hpin + (size_t)j * slot, h1, sizeof(double) * slot,
                               hipMemcpyDeviceToHost, st));
@@ -1017,7 +1021,7 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   S.N = m->ws.N;
   S.L = m->dm.n * 4 * S.N;
   S.restart = opts->restart;
-  S.nblk = 1024;
+  S.nblk = 1024;  // workgroups per vector slice of the Krylov reductions (upper bound)
   S.jv_kind = opts->jv_kind == HB_JV_PAPER ? HB_JV_PAPER : HB_JV_EXACT;
   const int N = S.N;
   const int64_t L = S.L;

@@ -117,6 +117,15 @@ hipError_t vec_dots(const T* Q, int64_t ld, int k, const T* w, int64_t L, double
 template <typename T>
 hipError_t vec_axpy_multi(T* w, const T* Q, int64_t ld, int k, const double* h, double sign,
                           int64_t L, hipStream_t st);
+// out[j] = Q_j . w, j < k (one partial-sum launch for all j, one reduction;
+// partial: k rows of nblk doubles)
+template <typename T>
+hipError_t vec_mdots(const T* Q, int64_t ld, int k, const T* w, int64_t L, double* partial,
+                     int nblk, double* out, hipStream_t st);
+// w -= sum_j h_j Q_j; out[0] = |w|^2 of the result (partial: nblk doubles)
+template <typename T>
+hipError_t vec_axpy_norm(T* w, const T* Q, int64_t ld, int k, const double* h, int64_t L,
+                         double* partial, int nblk, double* out, hipStream_t st);
 template <typename T>
 hipError_t vec_scale(T* x, int64_t L, double s, hipStream_t st);
 template <typename TD, typename TS>

@@ -1049,6 +1049,68 @@ k_reduce_rows(const double* __restrict__ partial, int nblk, double* __restrict__
   }
 }
 
+// Block sum of v into red (BLK / 64 slots); result valid in thread 0.
+__device__ inline double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < BLK / 64; ++q) t += red[q];
+  return t;
+}
+
+// Per-workgroup partial dot products Q_j . w for all j < k in one launch:
+// blockIdx.y selects a group of G basis vectors, blockIdx.x a slice of the
+// vectors; partial[j][blockIdx.x] (k_reduce_rows finishes the sums).
+template <int G, typename T>
+__global__ void __launch_bounds__(BLK)
+k_mdots(const T* __restrict__ Q, int64_t ld, int k, const T* __restrict__ w, int64_t L,
+        double* __restrict__ partial) {
+  __shared__ double red[BLK / 64];
+  const int k0 = blockIdx.y * G;
+  const int kc = min(G, k - k0);
+  const int nb = gridDim.x;
+  double acc[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc[j] = 0.0;
+  const int64_t stride = (int64_t)nb * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) {
+    const double wi = (double)w[i];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < kc) acc[j] += (double)Q[(int64_t)(k0 + j) * ld + i] * wi;
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const double t = block_sum(acc[j], red);
+    if (threadIdx.x == 0 && j < kc) partial[(int64_t)(k0 + j) * nb + blockIdx.x] = t;
+  }
+}
+
+// w -= sum_j h_j Q_j, with per-workgroup partials of |w|^2 of the result in
+// partial[blockIdx.x] (k_reduce_rows finishes the sum).
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_axpy_norm(T* __restrict__ w, const T* __restrict__ Q, int64_t ld, int k,
+            const double* __restrict__ h, int64_t L, double* __restrict__ partial) {
+  __shared__ double red[BLK / 64];
+  double s2 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride) {
+    double v = 0.0;
+    for (int j = 0; j < k; ++j) v += h[j] * (double)Q[(int64_t)j * ld + i];
+    const T wn = (T)((double)w[i] - v);
+    w[i] = wn;
+    s2 += (double)wn * (double)wn;
+  }
+  const double t = block_sum(s2, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_axpy_multi(T* __restrict__ w, const T* __restrict__ Q, int64_t ld, int k,
@@ -1295,6 +1357,33 @@ hipError_t vec_dots(const T* Q, int64_t ld, int k, const T* w, int64_t L, double
   return hipGetLastError();
 }
 
+// workgroups per vector slice for the fused reductions: >= 4 elements per
+// lane, at most nblk
+inline unsigned red_blocks(int64_t L, int nblk) {
+  const int64_t b = (L + 4 * BLK - 1) / (4 * BLK);
+  return (unsigned)(b < 1 ? 1 : (b > nblk ? nblk : b));
+}
+
+template <typename T>
+hipError_t vec_mdots(const T* Q, int64_t ld, int k, const T* w, int64_t L, double* partial,
+                     int nblk, double* out, hipStream_t st) {
+  const unsigned nb = red_blocks(L, nblk);
+  const unsigned groups = (unsigned)((k + 7) / 8);
+  hipLaunchKernelGGL((k_mdots<8, T>), dim3(nb, groups), dim3(BLK), 0, st, Q, ld, k, w, L,
+                     partial);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(BLK), 0, st, partial, (int)nb, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t vec_axpy_norm(T* w, const T* Q, int64_t ld, int k, const double* h, int64_t L,
+                         double* partial, int nblk, double* out, hipStream_t st) {
+  const unsigned nb = stream_blocks(L) < (unsigned)nblk ? stream_blocks(L) : (unsigned)nblk;
+  hipLaunchKernelGGL((k_axpy_norm<T>), dim3(nb), dim3(BLK), 0, st, w, Q, ld, k, h, L, partial);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(BLK), 0, st, partial, (int)nb, out);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t vec_axpy_multi(T* w, const T* Q, int64_t ld, int k, const double* h, double sign,
                           int64_t L, hipStream_t st) {
@@ -1379,6 +1468,10 @@ HB_INST_IO(float, double)
                                   double*, hipStream_t);                                        \
   template hipError_t vec_axpy_multi<T>(T*, const T*, int64_t, int, const double*, double,     \
                                         int64_t, hipStream_t);                                  \
+  template hipError_t vec_mdots<T>(const T*, int64_t, int, const T*, int64_t, double*, int,    \
+                                   double*, hipStream_t);                                       \
+  template hipError_t vec_axpy_norm<T>(T*, const T*, int64_t, int, const double*, int64_t,      \
+                                       double*, int, double*, hipStream_t);                     \
   template hipError_t vec_scale<T>(T*, int64_t, double, hipStream_t);                           \
   template hipError_t vec_scale_inv_norm<T>(T*, int64_t, const double*, hipStream_t);           \
   template hipError_t vec_zero<T>(T*, int64_t, hipStream_t);                                    \
