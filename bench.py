@@ -41,6 +41,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HB Jv throughput (GDOF-modes/s) + time to 1e-8 HB residual, mixed vs FP64"
+# precision names -> hb_solve_opts.precision (HB_F64, HB_MIXED, HB_F32_BASIS)
+PRECISIONS = {"fp64": 0, "mixed": 1, "f32_basis": 2}
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 # FP64 operations per (tetrahedron, sample) lane of the element kernels,
@@ -134,7 +136,7 @@ def womersley_time_to_solution(hbl, torch, log, precision="fp64"):
         t = time.time()
         r = hbl.newton_solve(gm, prm, bc, Y, hbl.SolveOptions(
             rtol=1e-8, max_newton=300, max_gmres=500,
-            precision=hbl.HB_MIXED if precision == "mixed" else hbl.HB_F64),
+            precision=PRECISIONS[precision]),
             raise_on_noconv=False)
         t_solve = time.time() - t
         res = {"workload": "womersley_pipe", "precision": precision, "n_nodes": n, "K": prm.K,
@@ -209,7 +211,8 @@ def main():
     ap.add_argument("--plain-newton", type=int, default=30)
     ap.add_argument("--max-gmres", type=int, default=300)
     ap.add_argument("--cfl-max", type=float, default=0.0)
-    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "f32_basis", "both"], default="both",
+                    help="'both': FP64 plus the two reduced-precision Krylov forms")
     ap.add_argument("--no-time-to-solution", action="store_true")
     ap.add_argument("--learned-train", type=int, default=384,
                     help="training solutions of the learned warm-start leg (0: skip it)")
@@ -346,9 +349,10 @@ def main():
                     "gmres_iters_per_step": [r["gmres_iters"] for r in reps],
                     "residual_per_step": [r["r_final"] for r in reps],
                     "jv_ms_avg": jv_ms / max(n_jv, 1)}
-        main_prec = "mixed" if args.precision == "mixed" else "fp64"
-        res = {p_: newton_steps(hbl.HB_MIXED if p_ == "mixed" else hbl.HB_F64)
-               for p_ in (["fp64", "mixed"] if args.precision == "both" else [main_prec])}
+        main_prec = "fp64" if args.precision == "both" else args.precision
+        res = {p_: newton_steps(PRECISIONS[p_])
+               for p_ in (["fp64", "mixed", "f32_basis"] if args.precision == "both"
+                          else [main_prec])}
         r0 = res[main_prec]
         out.update({"value": r0["jv_gdofs"], "steps": args.steps, "warmup": args.warmup,
                     "ms_per_step": r0["ms_per_step"],
@@ -358,8 +362,9 @@ def main():
                     "gmres_iters_per_step": r0["gmres_iters_per_step"],
                     "residual_per_step": r0["residual_per_step"],
                     "plain_start_s": plain_s, "jv_ms_avg": r0["jv_ms_avg"]})
-        if "mixed" in res and main_prec != "mixed":
-            out["mixed"] = res["mixed"]
+        for p_ in ("mixed", "f32_basis"):
+            if p_ in res and main_prec != p_:
+                out[p_] = res[p_]
         if not args.no_time_to_solution:
             out["time_to_1e8"] = {p_: womersley_time_to_solution(hbl, torch, log, p_)
                                   for p_ in res}

@@ -155,8 +155,11 @@ enum { HB_PREC_JACOBI = 0, HB_PREC_NODE_TIME = 1 };
 /* hb_solve_opts.precision: HB_F64 (= 0), or HB_MIXED: FP32 Krylov basis and
  * FP32 Jacobian-vector products (on an FP32 copy of the state) inside GMRES,
  * with the FP64 residual, FP64 Gram-Schmidt coefficients and FP64 Newton
- * update as the outer (iterative refinement) loop. */
-enum { HB_MIXED = 1 };
+ * update as the outer (iterative refinement) loop; or HB_F32_BASIS: FP32
+ * Krylov basis with FP64 Jacobian-vector products (the basis vectors are
+ * widened on entry to the operator and rounded on exit), same outer loop.
+ * Both reduced-precision forms require HB_JV_EXACT. */
+enum { HB_MIXED = 1, HB_F32_BASIS = 2 };
 
 typedef struct {
   double rtol;       /* stop when ||r||_2 <= rtol * r_ref (default 1e-8)              */
@@ -170,7 +173,7 @@ typedef struct {
   int32_t restart;   /* GMRES restart length (default 50)                             */
   int32_t max_newton;
   int32_t max_gmres; /* per Newton step                                               */
-  int32_t precision; /* HB_F64 or HB_MIXED                                           */
+  int32_t precision; /* HB_F64, HB_MIXED or HB_F32_BASIS                            */
   int32_t jv_kind;   /* HB_JV_EXACT or HB_JV_PAPER for the Krylov operator            */
   int32_t verbose;   /* print one line per Newton step to stderr                      */
   int32_t precond;   /* HB_PREC_JACOBI (the paper's diag(P)) or HB_PREC_NODE_TIME    */

@@ -21,6 +21,7 @@ HB_OK, HB_ERR_ARG, HB_ERR_MESH, HB_ERR_DEVICE, HB_ERR_NOCONV, HB_ERR_NAN, HB_ERR
     0, -1, -2, -3, -4, -5, -6)
 HB_JV_EXACT, HB_JV_PAPER, HB_F64, HB_F32 = 0, 1, 0, 2
 HB_MIXED = 1
+HB_F32_BASIS = 2
 HB_PREC_JACOBI, HB_PREC_NODE_TIME = 0, 1
 
 

@@ -740,6 +740,7 @@ struct Solver {
   int nblk;
   int jv_kind;
   const double* binv = nullptr;  // per-node time blocks, or NULL for the diagonal
+  bool jv64 = false;  // FP32 basis with FP64 Jacobian-vector products (HB_F32_BASIS)
   SolverBufs* sb = nullptr;
   double jv_ms = 0.0;
   int n_jv = 0;
@@ -791,7 +792,8 @@ struct Solver {
   // FP32 copy of the state (mixed precision), after every state change.
   int sync_state() {
     if constexpr (!std::is_same<T, double>::value)
-      HB_CHECK(hb::vec_copy_scaled<float, double>(m->ws.Sy32.as<float>(), m->ws.Sy.as<double>(),
+      if (!jv64)
+        HB_CHECK(hb::vec_copy_scaled<float, double>(m->ws.Sy32.as<float>(), m->ws.Sy.as<double>(),
                                                   m->dm.n * hb::NCH * N, 1.0, st));
     return HB_OK;
   }
@@ -831,6 +833,9 @@ struct Solver {
     Ptrs s = small_ptrs(m);
     const double* tab = w.tab.as<double>();
     const Phys p = make_phys(prm, shift);
+    if constexpr (!std::is_same<T, double>::value) {
+      if (jv64) return apply_f64(q, wout, p, s, tab);
+    }
     T* Sv = dir();
     T* acc = accum();
     const int pr = n_jv & 1;
@@ -855,6 +860,31 @@ struct Solver {
         return fail(HB_ERR_ARG, "the paper tangent is available in FP64 only");
       }
     }
+    HB_CHECK(hipEventRecord(sb->evj[2 * pr + 1], st));
+    jv_pending[pr] = true;
+    ++n_jv;
+    return HB_OK;
+  }
+
+  // FP32 basis vector in, FP64 Jacobian-vector product on the FP64 state,
+  // FP32 basis vector out.
+  int apply_f64(const T* q, T* wout, const Phys& p, const Ptrs& s, const double* tab) {
+    Workspace& w = m->ws;
+    double* Sv = w.Sv.as<double>();
+    double* acc = w.acc.as<double>();
+    const int pr = n_jv & 1;
+    if (jv_pending[pr]) {
+      int rc = collect_jv(pr);
+      if (rc) return rc;
+    }
+    HB_CHECK(hipEventRecord(sb->evj[2 * pr], st));
+    HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab,
+                                                Sv, acc, s.dQ, m->dm.n_out * N, st)));
+    if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, Sv, s.dQ, st));
+    HB_CHECK(hb::elem_jvp_exact<double>(m->dm, p, w.Sy.as<double>(), Sv, acc,
+                                        pick_blocks(m, N, sizeof(double)), st));
+    HB_CHECK(hb::face_jvp<double>(m->dm, p, w.Sy.as<double>(), Sv, s.R, s.dQ, acc, st));
+    HB_CHECK((hb::finish_rows<double, T>(m->dm, N, acc, 1, tab, q, wout, st)));
     HB_CHECK(hipEventRecord(sb->evj[2 * pr + 1], st));
     jv_pending[pr] = true;
     ++n_jv;
@@ -1023,6 +1053,7 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   S.restart = opts->restart;
   S.nblk = 1024;  // workgroups per vector slice of the Krylov reductions (upper bound)
   S.jv_kind = opts->jv_kind == HB_JV_PAPER ? HB_JV_PAPER : HB_JV_EXACT;
+  S.jv64 = opts->precision == HB_F32_BASIS;
   const int N = S.N;
   const int64_t L = S.L;
   int rc = S.alloc();
@@ -1127,9 +1158,9 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
   const auto t0 = std::chrono::steady_clock::now();
   std::memset(report, 0, sizeof(*report));
   report->status = HB_ERR_NOCONV;
-  if (opts->precision != HB_F64 && opts->precision != HB_MIXED)
-    return fail(HB_ERR_ARG, "precision must be HB_F64 or HB_MIXED");
-  if (opts->precision == HB_MIXED && opts->jv_kind == HB_JV_PAPER)
+  if (opts->precision != HB_F64 && opts->precision != HB_MIXED && opts->precision != HB_F32_BASIS)
+    return fail(HB_ERR_ARG, "precision must be HB_F64, HB_MIXED or HB_F32_BASIS");
+  if (opts->precision != HB_F64 && opts->jv_kind == HB_JV_PAPER)
     return fail(HB_ERR_ARG, "the mixed-precision solve uses the exact Jacobian");
   if (opts->restart < 1 || opts->restart > 512) return fail(HB_ERR_ARG, "restart must be 1..512");
   if (opts->max_newton < 0 || opts->max_gmres < 1) return fail(HB_ERR_ARG, "bad iteration limits");
@@ -1139,7 +1170,7 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
   hipStream_t st = (hipStream_t)stream;
   int rc = prepare(m, prm, bc, st);
   if (rc) return rc;
-  if (opts->precision == HB_MIXED) return newton_run<float>(m, prm, bc, Y, opts, report, st, t0);
+  if (opts->precision != HB_F64) return newton_run<float>(m, prm, bc, Y, opts, report, st, t0);
   return newton_run<double>(m, prm, bc, Y, opts, report, st, t0);
 }
 

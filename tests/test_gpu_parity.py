@@ -193,14 +193,16 @@ def test_jvp_f32_parity(case, request):
     assert rel(got, ref) <= TOL_F32
 
 
-def test_mixed_solve_matches_oracle_solution(c1):
-    """FP32 Krylov basis and Jv with the FP64 residual as the outer loop
-    reach the same FP64 root."""
+@pytest.mark.parametrize("precision", ["mixed", "f32_basis"])
+def test_mixed_solve_matches_oracle_solution(c1, precision):
+    """FP32 Krylov basis (with FP32 or FP64 Jv) and the FP64 residual as the
+    outer loop reach the same FP64 root."""
     g = np.load(os.path.join(HERE, "golden", "c1_solution.npz"))
     P = c1.P
     Y = dev(g["Y0"])
+    prec = hbl.HB_MIXED if precision == "mixed" else hbl.HB_F32_BASIS
     rep = hbl.newton_solve(c1.gm, P.params, c1.bc, Y,
                            hbl.SolveOptions(rtol=1e-12, max_newton=400, max_gmres=1000,
-                                            precision=hbl.HB_MIXED))
+                                            precision=prec))
     assert rep["status"] == 0
     assert rel(host(Y), g["Y"]) <= TOL
