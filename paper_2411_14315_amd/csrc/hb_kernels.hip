@@ -6,7 +6,9 @@
 //
 //   node tiles   modal <-> time-sample transforms and H products, one small
 //                dense N x N contraction per node and field, staged through
-//                LDS so that every global access is a contiguous run;
+//                LDS so that every global access is a contiguous run (FP64
+//                on the vector ALU; the FP32 paths run them as 32 x 32 tiles
+//                on the matrix cores with split-BF16 operands);
 //   elements     one quad of four lanes per (tetrahedron, sample) for the
 //                residual and exact Jacobian-vector kernels (lane A holds
 //                node A and quadrature point A; element sums and the row
@@ -22,6 +24,8 @@
 // [node][channel][sample], so the N lanes of one element read N contiguous
 // doubles per node and channel.
 #include "hb_internal.h"
+
+#include <type_traits>
 
 namespace hb {
 
@@ -85,6 +89,55 @@ __device__ __forceinline__ void xi_mul(const GeoT<R>& G, const R u[3], R o[3]) {
   o[2] = G.x02 * u[0] + G.x12 * u[1] + G.x22 * u[2];
 }
 
+// ------------------------------------------------------------ MFMA tiles
+
+// Time-axis contractions of the FP32 paths on the matrix cores: a 32 x 32
+// output tile C = A B (A: N x N time table or H, B: N x 32 node columns)
+// per wavefront, N padded to 32 rows and to a multiple of 8 in k.  Operands
+// are split into BF16 high and low parts, x = hi + lo, and three BF16 MFMAs
+// per k-step (hi.hi + hi.lo + lo.hi) accumulate in FP32, which keeps about
+// 16 significant bits of each product (split-BF16).
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ inline float bf16_val(short b) { return __uint_as_float((uint32_t)(uint16_t)b << 16); }
+
+// Lane layout of v_mfma_f32_32x32x8 (wavefront of 64): lane l supplies
+// A[l % 32][k0 + 4 (l / 32) + t] and B[k0 + 4 (l / 32) + t][l % 32], t < 4,
+// and holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in register r < 16.
+// FA(i, k) and FB(k, j) return 0 outside the matrices.
+template <class FA, class FB>
+__device__ inline f32x16 mfma_tile_split(int N, FA A, FB B) {
+  const int lane = threadIdx.x & 63;
+  const int ij = lane & 31, kq = (lane >> 5) * 4;
+  f32x16 c = {};
+  for (int k0 = 0; k0 < N; k0 += 8) {
+    bf16x4 ah, alo, bh, blo;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + kq + t;
+      const float a = (float)A(ij, k);
+      const float b = (float)B(k, ij);
+      const short a1 = bf16_rne(a), b1 = bf16_rne(b);
+      ah[t] = a1;
+      bh[t] = b1;
+      alo[t] = bf16_rne(a - bf16_val(a1));
+      blo[t] = bf16_rne(b - bf16_val(b1));
+    }
+    c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, blo, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(alo, bh, c, 0, 0, 0);
+  }
+  return c;
+}
+// row of register r of this lane in the C tile (the column is lane % 32)
+__device__ inline int mfma_row(int r) { return 8 * (r >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (r & 3); }
+
 // ------------------------------------------------------------ node tiles
 
 // Modal Y[f][m][a] -> samples S[a][c][s]: c = 0..3 values, 4..6 time
@@ -126,6 +179,29 @@ k_modal_to_samples(int64_t n, int N, const TI* __restrict__ Y, const double* __r
   if (qz && blockIdx.x == 0)
     for (int i = threadIdx.x; i < nq; i += BLK) qz[i] = 0.0;
   __syncthreads();
+  if constexpr (std::is_same<TO, float>::value) {
+    if (N <= 32 && TN == 32) {
+      // 7 tiles: Binv Y_f (f < 4) and Bder Y_f (f < 3), one per wavefront
+      const int lane = threadIdx.x & 63;
+      for (int tile = threadIdx.x >> 6; tile < 7; tile += BLK / 64) {
+        const int f = tile < 4 ? tile : tile - 4;
+        const double* T = tile < 4 ? sB : sD;
+        const f32x16 c = mfma_tile_split(
+            N, [&](int i, int k) { return (i < N && k < N) ? T[i * N + k] : 0.0; },
+            [&](int k, int j) { return k < N ? sY[(f * N + k) * TN + j] : 0.0; });
+        const int al = lane & 31;
+        if (al < tn) {
+          TO* out = S + (a0 + al) * NCH * N + tile * N;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int sr = mfma_row(r);
+            if (sr < N) out[sr] = c[r];
+          }
+        }
+      }
+      return;
+    }
+  }
   for (int it = threadIdx.x; it < tn * N; it += BLK) {
     const int al = it / N;
     const int s = it - al * N;
@@ -167,6 +243,36 @@ k_samples_to_modal(int64_t n, int N, const TA* __restrict__ acc, int use_z, int 
   const TA* ap = acc + a0 * CN;
   for (int i = threadIdx.x; i < tn * CN; i += BLK) sA[i] = (double)ap[i];
   __syncthreads();
+  if constexpr (std::is_same<TO, float>::value) {
+    if (N <= 32 && TN == 32) {
+      // 4 tiles (one per field): Fwd A_f, minus FwdD z_f on momentum rows
+      const int lane = threadIdx.x & 63;
+      const int f = threadIdx.x >> 6;  // BLK / 64 == 4 wavefronts, one field each
+      const bool wz = f < 3 && use_z;
+      const int K2 = wz ? 2 * N : N;   // [Fwd | -FwdD] against [A_f ; z_f]
+      const f32x16 c = mfma_tile_split(
+          K2,
+          [&](int i, int k) {
+            if (i >= N || k >= K2) return 0.0;
+            return k < N ? sF[i * N + k] : -sG[i * N + (k - N)];
+          },
+          [&](int k, int j) {
+            if (j >= tn || k >= K2) return 0.0;
+            const double* row = sA + j * CN;
+            return k < N ? row[f * N + k] : row[(4 + f) * N + (k - N)];
+          });
+      const int al = lane & 31;
+      if (al < tn) {
+        const bool zero = f < 3 && zero_dir_rows && dmask[a0 + al];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = mfma_row(r);
+          if (m < N) R[(int64_t)(f * N + m) * n + a0 + al] = zero ? TO(0) : (TO)c[r];
+        }
+      }
+      return;
+    }
+  }
   for (int it = threadIdx.x; it < 4 * N * tn; it += BLK) {
     const int al = it % tn;
     const int fm = it / tn;
@@ -246,6 +352,33 @@ k_prepare(int64_t n, int N, const TQ* q, int in_ch, const double* __restrict__ d
       v[2 * N + s] = v2;
     }
     __syncthreads();
+  }
+  if constexpr (std::is_same<TS, float>::value) {
+    if (N <= 32 && TN == 32) {
+      for (int it = threadIdx.x; it < tn * 4 * N; it += BLK) {
+        const int al = it / (4 * N);
+        const int r = it - al * 4 * N;
+        Sv[(a0 + al) * NCH * N + r] = (TS)sV[it];
+      }
+      // H v for the three velocity channels, one tile per wavefront
+      const int lane = threadIdx.x & 63;
+      const int c = threadIdx.x >> 6;
+      if (c < 3) {
+        const f32x16 hv = mfma_tile_split(
+            N, [&](int i, int k) { return (i < N && k < N) ? sH[i * N + k] : 0.0; },
+            [&](int k, int j) { return (k < N && j < tn) ? sV[j * 4 * N + c * N + k] : 0.0; });
+        const int al = lane & 31;
+        if (al < tn) {
+          TS* out = Sv + (a0 + al) * NCH * N + (4 + c) * N;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int sr = mfma_row(r);
+            if (sr < N) out[sr] = hv[r];
+          }
+        }
+      }
+      return;
+    }
   }
   for (int it = threadIdx.x; it < tn * N; it += BLK) {
     const int al = it / N;
@@ -375,6 +508,42 @@ k_finish(int64_t n, int N, const TA* __restrict__ acc, int use_z,
   const TA* ap = acc + a0 * NCH * N;
   for (int i = threadIdx.x; i < tn * NCH * N; i += BLK) sA[i] = (double)ap[i];
   __syncthreads();
+  if constexpr (std::is_same<TO, float>::value) {
+    if (N <= 32 && TN == 32 && use_z) {
+      // momentum rows: acc_c - H z_c on the matrix cores (one channel per
+      // wavefront); the pressure rows are copied
+      const int lane = threadIdx.x & 63;
+      const int c = threadIdx.x >> 6;
+      if (c < 3) {
+        const f32x16 hz = mfma_tile_split(
+            N, [&](int i, int k) { return (i < N && k < N) ? sH[i * N + k] : 0.0; },
+            [&](int k, int j) {
+              return (k < N && j < tn) ? sA[j * NCH * N + (4 + c) * N + k] : 0.0;
+            });
+        const int al = lane & 31;
+        if (al < tn) {
+          const int64_t a = a0 + al;
+          const double* row = sA + al * NCH * N;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int sr = mfma_row(r);
+            if (sr < N) {
+              const double v = dmask[a] ? (id_rows ? (double)id_rows[(a * 4 + c) * N + sr] : 0.0)
+                                         : row[c * N + sr] - (double)hz[r];
+              out[(a * 4 + c) * N + sr] = (TO)v;
+            }
+          }
+        }
+      } else {
+        for (int it = lane; it < tn * N; it += 64) {
+          const int al = it / N;
+          const int sr = it - al * N;
+          out[((a0 + al) * 4 + 3) * N + sr] = (TO)sA[al * NCH * N + 3 * N + sr];
+        }
+      }
+      return;
+    }
+  }
   for (int it = threadIdx.x; it < tn * 4 * N; it += BLK) {
     const int al = it / (4 * N);
     const int r = it - al * 4 * N;
