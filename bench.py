@@ -195,6 +195,63 @@ def learned_warm_start(torch, log, n_train, n_test, K=2):
     return out
 
 
+def branching_leg(hbl, torch, log, steps=3, plain_newton=10):
+    """Branching artery (1,255,132 nodes, 7,046,522 tets, K = 10, eight
+    resistance outlets): public Jv in FP64 and FP32, then `steps` inexact
+    Newton steps from the same plain start in FP64, HB_MIXED and
+    HB_F32_BASIS, with the reduced-precision states compared to the FP64
+    state after the same steps."""
+    from dataclasses import replace
+    from hbinputs.problems import c3_branching
+    t = time.time()
+    P = c3_branching()
+    log(f"branching artery mesh: {P.mesh.n_nodes} nodes, {P.mesh.n_tets} tets, {time.time() - t:.1f} s")
+    prm = P.params
+    n, N = P.mesh.n_nodes, prm.N
+    gm = hbl.Mesh.from_mesh(P.mesh)
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")  # noqa: E731
+    bc = hbl.BC(to(P.dirichlet), P.outlet_h, P.outlet_R)
+    bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
+    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
+    hbl.newton_solve(gm, replace(prm, K=0), bc0, Ys,
+                     hbl.SolveOptions(rtol=1e-10, max_newton=plain_newton, max_gmres=300),
+                     raise_on_noconv=False)
+    Y0 = torch.zeros((4, N, n), dtype=torch.float64, device="cuda:0")
+    Y0[:, 0] = Ys[:, 0]
+    dofs = 4.0 * n * N
+    V = Y0.clone()
+    out = {"workload": "branching_artery", "n_nodes": n, "n_tets": P.mesh.n_tets, "K": prm.K,
+           "outlets": int(P.outlet_R.size)}
+    for name, Vx in (("jv_fp64", V), ("jv_fp32", V.float())):
+        for _ in range(3):
+            hbl.jvp(gm, prm, bc, Y0, Vx)
+        torch.cuda.synchronize()
+        t = time.time()
+        for _ in range(10):
+            hbl.jvp(gm, prm, bc, Y0, Vx)
+        torch.cuda.synchronize()
+        ms = (time.time() - t) / 10 * 1e3
+        out[name] = {"ms": ms, "gdofs": dofs / (ms * 1e-3) / 1e9}
+    states = {}
+    for p_ in ("fp64", "mixed", "f32_basis"):
+        opts = hbl.SolveOptions(rtol=1e-30, max_newton=1, max_gmres=300, precision=PRECISIONS[p_])
+        Y = Y0.clone()
+        torch.cuda.synchronize()
+        t = time.time()
+        reps = [hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False) for _ in range(steps)]
+        torch.cuda.synchronize()
+        states[p_] = Y
+        out[p_] = {"ms_per_step": (time.time() - t) / steps * 1e3,
+                   "gmres_iters_per_step": [r["gmres_iters"] for r in reps],
+                   "residual_per_step": [r["r_final"] for r in reps]}
+        if p_ != "fp64":
+            out[p_]["state_rel_diff_vs_fp64"] = float(
+                torch.linalg.norm(Y - states["fp64"]) / torch.linalg.norm(states["fp64"]))
+    log(f"branching artery: {out}")
+    gm.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +274,9 @@ def main():
     ap.add_argument("--learned-train", type=int, default=384,
                     help="training solutions of the learned warm-start leg (0: skip it)")
     ap.add_argument("--learned-test", type=int, default=12)
+    ap.add_argument("--branching", type=int, default=0,
+                    help="Newton steps of the branching-artery leg (0: skip it; the mesh "
+                         "takes about a minute to generate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
@@ -368,6 +428,8 @@ def main():
         if not args.no_time_to_solution:
             out["time_to_1e8"] = {p_: womersley_time_to_solution(hbl, torch, log, p_)
                                   for p_ in res}
+        if args.branching > 0:
+            out["branching_artery"] = branching_leg(hbl, torch, log, args.branching)
         if args.learned_train > 0:
             out["learned_warm_start"] = learned_warm_start(torch, log, args.learned_train,
                                                            args.learned_test)

@@ -66,7 +66,7 @@ def boundary_faces(xyz, tets):
     opp = np.array([0, 1, 2, 3])
     f = tets[:, loc].reshape(-1, 3)
     other = tets[:, opp].reshape(-1)
-    key = np.sort(f, axis=1)
+    key = _face_keys(np.sort(f, axis=1))
     _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
     inv = inv.reshape(-1)
     keep = cnt[inv] == 1
@@ -78,6 +78,15 @@ def boundary_faces(xyz, tets):
     flip = s > 0
     f[flip, 1], f[flip, 2] = f[flip, 2].copy(), f[flip, 1].copy()
     return f.astype(np.int32)
+
+
+def _face_keys(sorted_faces):
+    """One int64 per sorted node triple when node ids fit in 21 bits (fast
+    1-D sorting); the triples themselves otherwise."""
+    f = np.asarray(sorted_faces, dtype=np.int64)
+    if f.size == 0 or f.max() < (1 << 21):
+        return (f[:, 0] << 42) | (f[:, 1] << 21) | f[:, 2]
+    return f
 
 
 def compact(xyz, tets):
@@ -92,11 +101,16 @@ def largest_component(xyz, tets):
     """Keep the face-connected component with the most tetrahedra."""
     loc = np.array([[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]])
     ne = tets.shape[0]
-    key = np.sort(tets[:, loc].reshape(-1, 3), axis=1)
+    key = _face_keys(np.sort(tets[:, loc].reshape(-1, 3), axis=1))
     owner = np.repeat(np.arange(ne), 4)
-    order = np.lexsort(key.T[::-1])
-    ks = key[order]
-    same = np.all(ks[1:] == ks[:-1], axis=1)
+    if key.ndim == 1:
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        same = ks[1:] == ks[:-1]
+    else:
+        order = np.lexsort(key.T[::-1])
+        ks = key[order]
+        same = np.all(ks[1:] == ks[:-1], axis=1)
     i = order[:-1][same]
     j = order[1:][same]
     g = sp.coo_matrix((np.ones(i.size), (owner[i], owner[j])), shape=(ne, ne))
@@ -353,3 +367,147 @@ def stenosed_pipe_mesh(severity: float, z_s: float, n_rings: int = 12, n_z: int 
     m = Mesh(xyz, base.tets, base.faces, base.face_group, base.group_kind,
              dict(base.info, kind="stenosed", severity=severity, z_s=z_s))
     return m
+
+
+# ------------------------------------------------------- branching artery
+
+def _arc_frame(d0, rng):
+    """A unit vector normal to d0, seeded."""
+    t = rng.normal(size=3)
+    t -= (t @ d0) * d0
+    return t / np.linalg.norm(t)
+
+
+def artery_tree(seed: int = 7, radii=(2.0, 1.26, 0.79, 0.50), length_factor: float = 6.0,
+                branch_angle: float = 0.5, max_turn: float = 0.35):
+    """Segments of a symmetric bifurcating tree: the root along +z from the
+    origin, each parent splitting into two children (radius ratio 0.63) at
+    +-branch_angle about a seeded axis; every segment is a circular arc of
+    length 6 r whose total turn is drawn from U[0, max_turn] about a seeded
+    normal.  Returns a list of dicts (p0, d0, n, kappa, L, r, level, end,
+    d_end)."""
+    rng = np.random.default_rng(seed)
+    segs = []
+
+    def add(p0, d0, level):
+        r = radii[level]
+        L = length_factor * r
+        n = _arc_frame(d0, rng)
+        turn = rng.uniform(0.0, max_turn)
+        kappa = max(turn / L, 1e-6)
+        ph = kappa * L
+        end = p0 + np.sin(ph) / kappa * d0 + (1.0 - np.cos(ph)) / kappa * n
+        d_end = np.cos(ph) * d0 + np.sin(ph) * n
+        segs.append(dict(p0=p0, d0=d0, n=n, kappa=kappa, L=L, r=r, level=level, end=end,
+                         d_end=d_end))
+        if level + 1 < len(radii):
+            ax = _arc_frame(d_end, rng)
+            for sgn in (1.0, -1.0):
+                dc = np.cos(branch_angle) * d_end + sgn * np.sin(branch_angle) * ax
+                add(end, dc / np.linalg.norm(dc), level + 1)
+
+    add(np.zeros(3), np.array([0.0, 0.0, 1.0]), 0)
+    return segs
+
+
+def _inside_arc(p, sg):
+    """Points within distance r of the arc (arclength in [0, L]), and the
+    arclength parameter of the nearest arc point."""
+    d = p - sg["p0"]
+    b = np.cross(sg["d0"], sg["n"])
+    u, v, w = d @ sg["d0"], d @ sg["n"], d @ b
+    k = sg["kappa"]
+    phi = np.arctan2(u * k, 1.0 - v * k)
+    ok = (phi >= 0.0) & (phi <= k * sg["L"])
+    du = u - np.sin(phi) / k
+    dv = v - (1.0 - np.cos(phi)) / k
+    return ok & (du * du + dv * dv + w * w <= sg["r"] ** 2)
+
+
+def branching_artery_mesh(h: float = 0.062, seed: int = 7, jitter: float = 0.15,
+                          jitter_seed: int = 1234, reorder_seed: int | None = 1234) -> Mesh:
+    """Carve a Kuhn lattice of spacing h to the union of the tree's arc tubes
+    and a ball of the parent radius at each branch point.  Only lattice
+    cells near each segment are generated.  Groups: 0 wall, 1 root inlet
+    (the plane z = 0), 2..9 the leaf outlets (faces within h of a leaf's end
+    plane and inside its radius)."""
+    segs = artery_tree(seed)
+    balls = [(sg["end"], sg["r"]) for sg in segs if sg["level"] + 1 < 4]
+    off = np.eye(3, dtype=np.int64)
+    perms = ([0, 1, 2], [0, 2, 1], [1, 0, 2], [1, 2, 0], [2, 0, 1], [2, 1, 0])
+    kept = []
+    for si, sg in enumerate(segs):
+        # bounding box of the arc (sampled) plus radius
+        tt = np.linspace(0.0, sg["L"], 64)
+        ph = sg["kappa"] * tt
+        pts = (sg["p0"] + np.outer(np.sin(ph) / sg["kappa"], sg["d0"])
+               + np.outer((1.0 - np.cos(ph)) / sg["kappa"], sg["n"]))
+        pad = sg["r"] * (1.0 if sg["level"] + 1 == 4 else 1.0) + 2 * h
+        if sg["level"] + 1 < 4:
+            pts = np.vstack([pts, sg["end"] + sg["r"], sg["end"] - sg["r"]])
+        lo = np.floor((pts.min(0) - pad) / h).astype(np.int64)
+        hi = np.ceil((pts.max(0) + pad) / h).astype(np.int64)
+        lo[2] = max(lo[2], 0)               # nothing below the inlet plane z = 0
+        gi = [np.arange(lo[a], hi[a]) for a in range(3)]
+        I, J, K = np.meshgrid(*gi, indexing="ij")
+        cells = np.stack([I.ravel(), J.ravel(), K.ravel()], 1)
+        cen = (cells + 0.5) * h
+        near = _inside_arc(cen, dict(sg, r=sg["r"] + h))
+        for (c, r) in balls:
+            near |= np.sum((cen - c) ** 2, axis=1) <= (r + h) ** 2
+        cells = cells[near]
+        for t, p in enumerate(perms):
+            c = np.zeros_like(cells)
+            vs = [cells.copy()]
+            for ax in p:
+                c = c + off[ax]
+                vs.append(cells + c)
+            v = np.stack(vs, 1)                         # (m, 4, 3) lattice points
+            cen_t = v.mean(axis=1) * h
+            ins = _inside_arc(cen_t, sg)
+            if sg["level"] + 1 < 4:
+                ins |= np.sum((cen_t - sg["end"]) ** 2, axis=1) <= sg["r"] ** 2
+            kept.append((v[ins], cells[ins], t))
+    # de-duplicate tetrahedra generated by more than one segment: key = (cell, type)
+    V = np.concatenate([k[0] for k in kept])
+    C = np.concatenate([k[1] for k in kept])
+    T = np.concatenate([np.full(k[1].shape[0], k[2]) for k in kept])
+    base = C.min(0)
+    span = C.max(0) - base + 2
+    lin = ((C[:, 0] - base[0]) * span[1] + (C[:, 1] - base[1])) * span[2] + (C[:, 2] - base[2])
+    _, first = np.unique(lin * 6 + T, return_index=True)
+    V = V[first]
+    vb = V.reshape(-1, 3) - base
+    vid = (vb[:, 0] * span[1] + vb[:, 1]) * span[2] + vb[:, 2]
+    uniq, inv = np.unique(vid, return_inverse=True)
+    tets = inv.reshape(-1, 4)
+    iz = uniq % span[2]
+    iy = (uniq // span[2]) % span[1]
+    ix = uniq // (span[1] * span[2])
+    xyz = (np.stack([ix, iy, iz], 1) + base) * h
+    xyz, tets = largest_component(xyz, tets.astype(np.int64))
+    tets = orient_positive(xyz, tets)
+    faces = boundary_faces(xyz, tets)
+    bnd = np.zeros(xyz.shape[0], bool)
+    bnd[faces.ravel()] = True
+    if jitter > 0:
+        rng = np.random.default_rng(jitter_seed)
+        inner = ~bnd
+        xyz = xyz.copy()
+        xyz[inner] += rng.uniform(-jitter * h, jitter * h, size=(int(inner.sum()), 3))
+    grp = np.zeros(faces.shape[0], np.int32)
+    fc = xyz[faces].mean(axis=1)
+    fz = xyz[faces][:, :, 2]
+    grp[np.all(np.abs(fz) < 1e-9, axis=1)] = 1
+    leaves = [sg for sg in segs if sg["level"] == 3]
+    for li, sg in enumerate(leaves):
+        d = fc - sg["end"]
+        ax = d @ sg["d_end"]
+        lat = np.linalg.norm(d - np.outer(ax, sg["d_end"]), axis=1)
+        grp[(grp == 0) & (np.abs(ax) < h) & (lat < sg["r"] - 0.25 * h)] = 2 + li
+    kinds = np.array([WALL, INLET] + [OUTLET] * len(leaves), np.int32)
+    m = Mesh(xyz, tets.astype(np.int32), faces, grp, kinds,
+             dict(kind="branching_artery", h=h, seed=seed, r_root=2.0, n_leaves=len(leaves),
+                  inlets=[dict(group=1, center=(0.0, 0.0, 0.0), normal=(0.0, 0.0, 1.0),
+                               radius=2.0)]))
+    return rcm_reorder(m, seed=reorder_seed)

@@ -14,7 +14,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .meshes import INLET, OUTLET, WALL, Mesh, cylinder_mesh, stenosed_pipe_mesh, tjunction_mesh
+from .meshes import (INLET, OUTLET, WALL, Mesh, branching_artery_mesh, cylinder_mesh,
+                     stenosed_pipe_mesh, tjunction_mesh)
 
 RHO = 1.06   # g/cm^3, whole blood
 MU = 0.04    # poise (4 mPa s)
@@ -122,6 +123,25 @@ def c2_tjunction(K: int = 10, h: float = 3.0 / 70.0, reynolds: float = 500.0,
     nout = n_outlets(mesh)
     R = np.full(nout, p_ref * nout / (2.0 * qbar)) if resistance else None
     return Problem("c2_tjunction", mesh, prm, dirv, np.zeros((nout, prm.N)), R, u_ref=ubar)
+
+
+def c3_branching(K: int = 10, h: float = 0.062, reynolds: float = 500.0,
+                 p_ref: float = 1.0e4) -> Problem:
+    """Curved branching artery: three bifurcation generations (radii 2.0,
+    1.26, 0.79, 0.50, segment length 6 r, seeded arc curvature, seed 7),
+    root inflow built like the T-junction's (seed 13, Re on the root
+    diameter), eight resistance outlets R = 8 p_ref / Q (each outlet takes
+    Q / 8 at pressure p_ref)."""
+    mesh = branching_artery_mesh(h=h)
+    prm = Params(period=1.0, K=K)
+    r0 = mesh.info["r_root"]
+    ubar = reynolds * prm.mu / (prm.rho * 2.0 * r0)
+    qbar = ubar * np.pi * r0 ** 2
+    dirv = poiseuille_dirichlet(mesh, K, [seeded_waveform(K, qbar, 13)])
+    nout = n_outlets(mesh)
+    R = np.full(nout, p_ref * nout / qbar)
+    return Problem("c3_branching_artery", mesh, prm, dirv, np.zeros((nout, prm.N)), R,
+                   u_ref=ubar)
 
 
 def c4_stenosis_params(n: int, seed: int, K: int = 10, reynolds: float = 100.0,

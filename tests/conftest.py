@@ -8,4 +8,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built library")
-    config.addinivalue_line("markers", "slow: CPU test that takes more than ~20 s")
+    config.addinivalue_line("markers", "slow: test that takes more than ~20 s")

@@ -13,7 +13,8 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import paper_2411_14315_amd as hbl  # noqa: E402
-from hbinputs.problems import Params, c1_womersley, c2_tjunction, seeded_state  # noqa: E402
+from hbinputs.problems import (Params, c1_womersley, c2_tjunction, c3_branching,  # noqa: E402
+                               c4_stenosed, c4_stenosis_params, seeded_state)
 from oracle import api, fem, spectral  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -143,6 +144,65 @@ def test_full_size_sampled_rows(tj_full):
     refj = api.jvp_modal(om, prm, Y, V, d, h, R, rows=rows)[:, :, rows]
     gotj = host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V)))[:, :, rows]
     assert rel(gotj, refj) <= TOL
+
+
+@pytest.fixture(scope="module")
+def art():
+    """Coarse branching artery (h = 0.25, ~23k nodes, K = 4): eight
+    resistance outlets, curved oblique outlet caps."""
+    return Case(c3_branching(K=4, h=0.25))
+
+
+def test_branching_coarse_parity(art):
+    c = art
+    om, prm, d, h, R = c.args()
+    Y, V = seeded_state(c.P, 15), seeded_state(c.P, 16)
+    ref = api.residual_modal(om, prm, Y, d, h, R)
+    assert rel(host(hbl.residual(c.gm, prm, c.bc, dev(Y))), ref) <= TOL
+    refj = api.jvp_modal(om, prm, Y, V, d, h, R)
+    assert rel(host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V))), refj) <= TOL
+    got32 = host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V).float())).astype(np.float64)
+    assert rel(got32, refj) <= TOL_F32
+
+
+def _sampled_rows(om, seed):
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(om.n, 64, replace=False))
+    return np.union1d(rows, om.ofaces[rng.choice(om.ofaces.shape[0], 8, replace=False)].ravel())
+
+
+@pytest.mark.slow
+def test_branching_full_size_sampled_rows():
+    """Full-size branching artery (1,255,132 nodes, 7,046,522 tetrahedra,
+    K = 10, eight resistance outlets): FP64 residual and exact Jv rows, and
+    FP32 Jv rows, at seeded random nodes and outlet-face nodes."""
+    c = Case(c3_branching())
+    om, prm, d, h, R = c.args()
+    rows = _sampled_rows(om, 1)
+    Y, V = seeded_state(c.P, 17), seeded_state(c.P, 18)
+    ref = api.residual_modal(om, prm, Y, d, h, R, rows=rows)[:, :, rows]
+    got = host(hbl.residual(c.gm, prm, c.bc, dev(Y)))[:, :, rows]
+    assert rel(got, ref) <= TOL
+    refj = api.jvp_modal(om, prm, Y, V, d, h, R, rows=rows)[:, :, rows]
+    gotj = host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V)))[:, :, rows]
+    assert rel(gotj, refj) <= TOL
+    got32 = host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V).float()))[:, :, rows]
+    assert rel(got32.astype(np.float64), refj) <= TOL_F32
+
+
+@pytest.mark.slow
+def test_stenosed_full_size_sampled_rows():
+    """Full-size stenosed pipe of the learned family (12 rings x 90 stations,
+    K = 10, 23 parameters): residual and exact Jv rows."""
+    theta = c4_stenosis_params(1, 2024, K=10)[0]
+    c = Case(c4_stenosed(theta, K=10))
+    om, prm, d, h, R = c.args()
+    rows = _sampled_rows(om, 2)
+    Y, V = seeded_state(c.P, 19), seeded_state(c.P, 20)
+    ref = api.residual_modal(om, prm, Y, d, h, R, rows=rows)[:, :, rows]
+    assert rel(host(hbl.residual(c.gm, prm, c.bc, dev(Y)))[:, :, rows], ref) <= TOL
+    refj = api.jvp_modal(om, prm, Y, V, d, h, R, rows=rows)[:, :, rows]
+    assert rel(host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V)))[:, :, rows], refj) <= TOL
 
 
 def test_solve_matches_oracle_solution(c1):
