@@ -76,10 +76,11 @@ def elem_traffic(n, ne, K):
 def elem_bytes(n, ne, N, kind):
     """Algorithmic HBM bytes of one element-kernel launch: node samples read
     once (7 channels of state, 7 of direction for Jv), accumulator rows
-    read-modify-written once (7 channels), geometry (17 doubles) and
+    read-modify-written once (7 channels), geometry (20 doubles: each lane
+    of a quad reads its own node gradient) and
     connectivity (4 int32) once per tetrahedron."""
     node_ch = 14 if kind != "residual" else 7
-    return 8.0 * n * N * (node_ch + 2 * 7) + ne * (17 * 8 + 4 * 4)
+    return 8.0 * n * N * (node_ch + 2 * 7) + ne * (20 * 8 + 4 * 4)
 
 
 def cpu_baseline(P, Y, V, budget_s=30.0):

@@ -183,6 +183,7 @@ Phys make_phys(const hb_params* prm, double shift) {
   p.rho = prm->rho;
   p.mu = prm->mu;
   p.nu = prm->mu / prm->rho;
+  p.inv_rho = 1.0 / prm->rho;
   p.C_I = prm->C_I;
   p.beta = prm->beta_bf;
   p.omega = 6.283185307179586476925286766559 / prm->period;
@@ -412,6 +413,8 @@ int hb_mesh_create(int64_t n_nodes, const double* xyz, int64_t n_tets, const int
       Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
       for (int k = 0; k < 3; ++k)
         for (int i = 0; i < 3; ++i) geo[(size_t)(hb::GEO_G1 + 3 * k + i) * ne + t] = Ji[k][i];
+      for (int i = 0; i < 3; ++i)
+        geo[(size_t)(hb::GEO_G0 + i) * ne + t] = -(Ji[0][i] + Ji[1][i] + Ji[2][i]);
       geo[(size_t)hb::GEO_V * ne + t] = det / 6.0;
       double xi[3][3];
       for (int i = 0; i < 3; ++i)

@@ -38,16 +38,19 @@ struct ElemBlocks {
   const uint8_t* slot = nullptr;   // [4][ne] slot of element node A in its block
 };
 
-// Per-tetrahedron geometry rows: gradients of N_1..N_3 (N_0 = -sum), volume,
-// the upper triangle of xi = J^-T J^-1 and xi:xi.
+// Per-tetrahedron geometry rows: gradients of N_1..N_3, volume, the upper
+// triangle of xi = J^-T J^-1, xi:xi, and grad N_0 = -sum of the others.
 enum {
   GEO_G1 = 0, GEO_G2 = 3, GEO_G3 = 6, GEO_V = 9,
   GEO_XI00 = 10, GEO_XI01 = 11, GEO_XI02 = 12, GEO_XI11 = 13, GEO_XI12 = 14, GEO_XI22 = 15,
-  GEO_XIXI = 16, GEO_COUNT = 17
+  GEO_XIXI = 16,
+  GEO_G0 = 17,  // grad N_0 = -(grad N_1 + grad N_2 + grad N_3), stored for the quad-lane kernels
+  GEO_COUNT = 20
 };
 
 struct Phys {
   double rho, mu, nu, C_I, beta, omega;
+  double inv_rho;    // 1 / rho
   double shift;      // pseudo-time mass coefficient on velocity rows (0 = none)
   int32_t N;
   int32_t backflow;  // 1 = backflow term on outlets

@@ -82,6 +82,23 @@ __device__ __forceinline__ void load_geo(const double* __restrict__ geo, int64_t
   G.xixi = geo[GEO_XIXI * ne + t];
 }
 
+// tau = 1 / sqrt(x), x > 0: the hardware reciprocal-square-root estimate
+// refined by Newton steps y <- y + y (1 - x y^2) / 2 (two in FP64, one in
+// FP32), each of which doubles the number of correct bits.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+  }
+  return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
+
 template <typename R>
 __device__ __forceinline__ void xi_mul(const GeoT<R>& G, const R u[3], R o[3]) {
   o[0] = G.x00 * u[0] + G.x01 * u[1] + G.x02 * u[2];
@@ -606,7 +623,7 @@ template <int CTRL>
 __device__ __forceinline__ float quad_swap(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
-constexpr int XOR1 = 0xB1, XOR2 = 0x4E;
+constexpr int XOR1 = 0xB1, XOR2 = 0x4E, XOR3 = 0x1B;  // quad_perm [1,0,3,2], [2,3,0,1], [3,2,1,0]
 
 template <typename R>
 __device__ __forceinline__ R quad_sum(R v) {
@@ -615,28 +632,39 @@ __device__ __forceinline__ R quad_sum(R v) {
   return v;
 }
 
-// cr[B][c] (contributions of this lane to node B, channel c) -> the sum
-// over the quad of cr[A][c] for this lane's A.
+// Relative order: lane A holds ck[k][c], its contribution to node A ^ k.
+// Lane A ^ k's entry k is its contribution to node A, so one exchange per k
+// collects node A's rows without lane-dependent selects.
 template <typename R>
-__device__ __forceinline__ void quad_reduce_scatter(int A, R cr[4][NCH], R out[NCH]) {
-  const bool hi = (A & 2) != 0, lo = (A & 1) != 0;
+__device__ __forceinline__ void quad_gather_rows(R ck[4][NCH], R out[NCH]) {
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    const R k0 = hi ? cr[2][c] : cr[0][c];
-    const R k1 = hi ? cr[3][c] : cr[1][c];
-    const R s0 = hi ? cr[0][c] : cr[2][c];
-    const R s1 = hi ? cr[1][c] : cr[3][c];
-    const R r0 = k0 + quad_swap<XOR2>(s0);
-    const R r1 = k1 + quad_swap<XOR2>(s1);
-    out[c] = (lo ? r1 : r0) + quad_swap<XOR1>(lo ? r0 : r1);
-  }
+  for (int c = 0; c < NCH; ++c)
+    out[c] = ck[0][c] + quad_swap<XOR1>(ck[1][c]) + quad_swap<XOR2>(ck[2][c]) +
+             quad_swap<XOR3>(ck[3][c]);
 }
 
+// Element geometry as seen by lane A of a quad: g[k] = grad N_(A ^ k) (its
+// own gradient loaded, the others exchanged within the quad), the volume
+// and xi.
 template <typename R>
-__device__ __forceinline__ void pick_grad(const GeoT<R>& G, int A, R g[3]) {
+__device__ __forceinline__ void load_geo_lane(const double* __restrict__ geo, int64_t ne,
+                                              int64_t t, int A, GeoT<R>& G) {
+  const int row = A == 0 ? GEO_G0 : GEO_G1 + 3 * (A - 1);
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-    g[i] = A == 0 ? G.g[0][i] : A == 1 ? G.g[1][i] : A == 2 ? G.g[2][i] : G.g[3][i];
+  for (int i = 0; i < 3; ++i) {
+    G.g[0][i] = (R)geo[(row + i) * ne + t];
+    G.g[1][i] = quad_swap<XOR1>(G.g[0][i]);
+    G.g[2][i] = quad_swap<XOR2>(G.g[0][i]);
+    G.g[3][i] = quad_swap<XOR3>(G.g[0][i]);
+  }
+  G.V = geo[GEO_V * ne + t];
+  G.x00 = geo[GEO_XI00 * ne + t];
+  G.x01 = geo[GEO_XI01 * ne + t];
+  G.x02 = geo[GEO_XI02 * ne + t];
+  G.x11 = geo[GEO_XI11 * ne + t];
+  G.x12 = geo[GEO_XI12 * ne + t];
+  G.x22 = geo[GEO_XI22 * ne + t];
+  G.xixi = geo[GEO_XIXI * ne + t];
 }
 
 // Residual of eq. Rmc for one (tetrahedron, sample):
@@ -651,10 +679,9 @@ __device__ __forceinline__ int64_t residual_lane(const DevMesh& m, const Phys& p
                                                  const double* __restrict__ S, int64_t t, int s,
                                                  int A, double res[NCH]) {
   const int N = p.N;
-  Geo G;
-  load_geo(m.geo, m.ne, t, G);
-  double gA[3];
-  pick_grad(G, A, gA);
+  Geo G;  // G.g[k] = grad N_(A ^ k)
+  load_geo_lane(m.geo, m.ne, t, A, G);
+  const double* gA = G.g[0];
   const int64_t base = (int64_t)m.tets[A * m.ne + t] * NCH * N + s;
   const double* q = S + base;
   double u[3], hu[3];
@@ -681,25 +708,25 @@ __device__ __forceinline__ int64_t residual_lane(const DevMesh& m, const Phys& p
   for (int i = 0; i < 3; ++i) adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
   xi_mul(G, uq, xu);
   const double tau =
-      1.0 / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + p.C_I * p.nu * p.nu * G.xixi);
+      rsqrt_nr(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + p.C_I * p.nu * p.nu * G.xixi);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     gal[i] = rho * (hq[i] + adv[i]);
     sv[i] = tau * (gal[i] + gp[i]);
   }
-  double cr[4][NCH];
+  double cr[4][NCH];  // cr[k]: contributions to node A ^ k
 #pragma unroll
   for (int B = 0; B < 4; ++B) {
-    const double NB = (B == A) ? QA : QB;
+    const double NB = (B == 0) ? QA : QB;
     const double c = uq[0] * G.g[B][0] + uq[1] * G.g[B][1] + uq[2] * G.g[B][2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       cr[B][i] = w * (NB * gal[i] + c * sv[i]);
       cr[B][4 + i] = w * NB * sv[i];
     }
-    cr[B][3] = w * (G.g[B][0] * sv[0] + G.g[B][1] * sv[1] + G.g[B][2] * sv[2]) / rho;
+    cr[B][3] = w * p.inv_rho * (G.g[B][0] * sv[0] + G.g[B][1] * sv[1] + G.g[B][2] * sv[2]);
   }
-  quad_reduce_scatter(A, cr, res);
+  quad_gather_rows(cr, res);
   const double V = G.V;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -717,10 +744,9 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
                                                   const R* __restrict__ Sv, int64_t t, int s,
                                                   int A, R res[NCH]) {
   const int N = p.N;
-  GeoT<R> G;
-  load_geo(m.geo, m.ne, t, G);
-  R gA[3];
-  pick_grad(G, A, gA);
+  GeoT<R> G;  // G.g[k] = grad N_(A ^ k)
+  load_geo_lane(m.geo, m.ne, t, A, G);
+  const R* gA = G.g[0];
   const int64_t base = (int64_t)m.tets[A * m.ne + t] * NCH * N + s;
   const R* q = Sy + base;
   const R* d = Sv + base;
@@ -761,7 +787,7 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
   }
   xi_mul(G, uq, xu);
   const R tau =
-      R(1) / sqrt(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + R(p.C_I * p.nu * p.nu) * G.xixi);
+      rsqrt_nr(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + R(p.C_I * p.nu * p.nu) * G.xixi);
   const R dtau = -tau * tau * tau * (xu[0] * duq[0] + xu[1] * duq[1] + xu[2] * duq[2]);
   R sv[3], ds[3], dgal[3];
 #pragma unroll
@@ -771,10 +797,10 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
     sv[i] = tau * L;
     ds[i] = dtau * L + tau * (dgal[i] + dgp[i]);
   }
-  R cr[4][NCH];
+  R cr[4][NCH];  // cr[k]: contributions to node A ^ k
 #pragma unroll
   for (int B = 0; B < 4; ++B) {
-    const R NB = (B == A) ? R(QA) : R(QB);
+    const R NB = (B == 0) ? R(QA) : R(QB);
     const R c = uq[0] * G.g[B][0] + uq[1] * G.g[B][1] + uq[2] * G.g[B][2];
     const R dc = duq[0] * G.g[B][0] + duq[1] * G.g[B][1] + duq[2] * G.g[B][2];
 #pragma unroll
@@ -782,9 +808,9 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
       cr[B][i] = w * (NB * dgal[i] + dc * sv[i] + c * ds[i]);
       cr[B][4 + i] = w * NB * ds[i];
     }
-    cr[B][3] = w * (G.g[B][0] * ds[0] + G.g[B][1] * ds[1] + G.g[B][2] * ds[2]) / rho;
+    cr[B][3] = w * R(p.inv_rho) * (G.g[B][0] * ds[0] + G.g[B][1] * ds[1] + G.g[B][2] * ds[2]);
   }
-  quad_reduce_scatter(A, cr, res);
+  quad_gather_rows(cr, res);
   const R V = G.V;
   const R ms = R(p.shift) * V * R(1.0 / 20.0);
 #pragma unroll
