@@ -291,8 +291,8 @@ int ensure_f32(hb_mesh* m) {
 #ifndef HB_LDS_BUDGET
 #define HB_LDS_BUDGET (64 * 1024)
 #endif
-// Largest element block whose LDS accumulator (unique nodes x 7 x N values
-// of `elem` bytes) stays within the LDS budget per workgroup.
+// Largest element block whose LDS accumulator (unique nodes x 7 x N FP64
+// values, in every precision) stays within the LDS budget per workgroup.
 const hb::ElemBlocks& pick_blocks(const hb_mesh* m, int N, size_t elem = sizeof(double)) {
   for (const auto& b : m->bmaps)
     if ((size_t)b.eb.max_unique * hb::NCH * N * elem <= HB_LDS_BUDGET) return b.eb;
@@ -667,7 +667,7 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
     if (s.R) HB_CHECK(hb::outlet_flux<float>(m->dm, N, Sv32, s.dQ, st));
     HB_CHECK(mark(m, 3, st));
     HB_CHECK(hb::elem_jvp_exact<float>(m->dm, p, Sy32, Sv32, acc32,
-                                       pick_blocks(m, N, sizeof(float)), st));
+                                       pick_blocks(m, N), st));
     HB_CHECK(mark(m, 4, st));
     HB_CHECK(hb::face_jvp<float>(m->dm, p, Sy32, Sv32, s.R, s.dQ, acc32, st));
     HB_CHECK(mark(m, 5, st));
@@ -851,7 +851,7 @@ struct Solver {
                                          acc, s.dQ, m->dm.n_out * N, st));
     if (jv_kind == HB_JV_EXACT) {
       if (s.R) HB_CHECK(hb::outlet_flux<T>(m->dm, N, Sv, s.dQ, st));
-      HB_CHECK(hb::elem_jvp_exact<T>(m->dm, p, state(), Sv, acc, pick_blocks(m, N, sizeof(T)),
+      HB_CHECK(hb::elem_jvp_exact<T>(m->dm, p, state(), Sv, acc, pick_blocks(m, N),
                                      st));
       HB_CHECK(hb::face_jvp<T>(m->dm, p, state(), Sv, s.R, s.dQ, acc, st));
       HB_CHECK(hb::finish_rows<T, T>(m->dm, N, acc, 1, tab, q, wout, st));
@@ -885,7 +885,7 @@ struct Solver {
                                                 Sv, acc, s.dQ, m->dm.n_out * N, st)));
     if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, Sv, s.dQ, st));
     HB_CHECK(hb::elem_jvp_exact<double>(m->dm, p, w.Sy.as<double>(), Sv, acc,
-                                        pick_blocks(m, N, sizeof(double)), st));
+                                        pick_blocks(m, N), st));
     HB_CHECK(hb::face_jvp<double>(m->dm, p, w.Sy.as<double>(), Sv, s.R, s.dQ, acc, st));
     HB_CHECK((hb::finish_rows<double, T>(m->dm, N, acc, 1, tab, q, wout, st)));
     HB_CHECK(hipEventRecord(sb->evj[2 * pr + 1], st));

@@ -832,8 +832,9 @@ template <int KIND, typename R>
 __global__ void __launch_bounds__(BLK)
 k_elem_block(DevMesh m, Phys p, const R* __restrict__ Sy, const R* __restrict__ Sv,
              R* __restrict__ acc, ElemBlocks eb, int64_t nlogical) {
-  extern __shared__ double smem[];
-  R* sacc = reinterpret_cast<R*>(smem);  // [U][NCH][N]
+  // [U][NCH][N], FP64 also in the FP32 kernel: 32-bit LDS atomics on this
+  // access pattern stall on bank conflicts, 64-bit ones do not
+  extern __shared__ double sacc[];
   const int64_t b = xcd_block(nlogical);
   if (b < 0) return;
   const int N = p.N;
@@ -842,7 +843,7 @@ k_elem_block(DevMesh m, Phys p, const R* __restrict__ Sy, const R* __restrict__ 
   const int nel = (int)min<int64_t>(eb.size, m.ne - e0);
   const int32_t p0 = eb.ptr[b];
   const int U = eb.ptr[b + 1] - p0;
-  for (int i = threadIdx.x; i < U * CN; i += BLK) sacc[i] = R(0);
+  for (int i = threadIdx.x; i < U * CN; i += BLK) sacc[i] = 0.0;
   __syncthreads();
   const int total = nel * N * 4;
   for (int it = threadIdx.x; it < total; it += BLK) {  // quads stay aligned (BLK % 4 == 0)
@@ -856,16 +857,17 @@ k_elem_block(DevMesh m, Phys p, const R* __restrict__ Sy, const R* __restrict__ 
       residual_lane(m, p, Sy, t, s, A, r);
     else
       jvp_exact_lane<R>(m, p, Sy, Sv, t, s, A, r);
-    R* dst = sacc + eb.slot[A * m.ne + t] * CN + s;
+    double* dst = sacc + eb.slot[A * m.ne + t] * CN + s;
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
-      __hip_atomic_fetch_add(dst + c * N, r[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(dst + c * N, (double)r[c], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < U * CN; i += BLK) {
     const int u = i / CN;
     const int r = i - u * CN;
-    atomic_add(acc + (int64_t)eb.nodes[p0 + u] * CN + r, sacc[i]);
+    atomic_add(acc + (int64_t)eb.nodes[p0 + u] * CN + r, (R)sacc[i]);
   }
 }
 
@@ -1494,7 +1496,7 @@ template <typename R>
 hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const R* Sy, const R* Sv, R* acc,
                           const ElemBlocks& eb, hipStream_t st) {
   const int64_t nb = (m.ne + eb.size - 1) / eb.size;
-  const size_t lds = sizeof(R) * (size_t)eb.max_unique * NCH * p.N;
+  const size_t lds = sizeof(double) * (size_t)eb.max_unique * NCH * p.N;
   hipLaunchKernelGGL((k_elem_block<1, R>), dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, Sy, Sv,
                      acc, eb, nb);
   return hipGetLastError();
