@@ -166,11 +166,12 @@ def learned_warm_start(torch, log, n_train, n_test, K=2):
     rank = min(64, n_train // 2)
     model = learned.WarmStart(rank=rank, hidden=(256, 256)).fit(th, Y, Y0, steps=4000, lr=2e-3)
     log(f"learned: fit in {model.fit_s:.1f} s, loss {model.losses[0]:.3g} -> {model.losses[-1]:.3g}")
-    rows = []
+    rows, rows_mixed = [], []
     for x in tt:
         case = learned.Case.build(c4_stenosed(x, K=K, **kw))
         case.solve(case.plain_start(), 0.0, 1e-8)       # warm caches, untimed
         rows.append(learned.compare_starts(model, case, x))
+        rows_mixed.append(learned.compare_starts(model, case, x, precision=PRECISIONS["mixed"]))
         case.mesh.close()
 
     def avg(k, f):
@@ -189,6 +190,13 @@ def learned_warm_start(torch, log, n_train, n_test, K=2):
                   "solve_s": avg(k, lambda r: r["wall_s"]),
                   "total_s": avg(k, lambda r: r["start_s"] + r["wall_s"]),
                   "start_rel_error": avg(k, lambda r: r["start_err"])}
+    # the same comparison with mixed-precision (HB_MIXED) solves
+    for k in ("plain", "learned"):
+        out[k + "_mixed"] = {
+            "newton_iters": float(np.mean([r[k]["newton_iters"] for r in rows_mixed])),
+            "gmres_iters": float(np.mean([r[k]["gmres_iters"] for r in rows_mixed])),
+            "total_s": float(np.mean([r[k]["start_s"] + r[k]["wall_s"] for r in rows_mixed])),
+            "converged": int(sum(r[k]["status"] == 0 for r in rows_mixed))}
     # residual of the start relative to the plain start's, per draw
     out["learned"]["start_residual_ratio"] = float(np.mean(
         [r["learned"]["r_start"] / r["plain"]["r_start"] for r in rows]))
@@ -253,6 +261,52 @@ def branching_leg(hbl, torch, log, steps=3, plain_newton=10):
     return out
 
 
+def cfl_study(hbl, torch, log, workload="tjunction", cfls=(0.25, 1.0, 4.0, 16.0), steps=40):
+    """Pseudo-time step study (Section 2.3 sets dt ~ h_c / u_c): FP64 Newton
+    steps from the plain start with the pseudo step held fixed at
+    dt = cfl h_c / u_c (no growth), recording the residual relative to the
+    plain start's after every step."""
+    from dataclasses import replace
+    from hbinputs.problems import c1_womersley, c2_tjunction
+    P = c2_tjunction(K=10) if workload == "tjunction" else c1_womersley()
+    prm = P.params
+    n, N = P.mesh.n_nodes, prm.N
+    gm = hbl.Mesh.from_mesh(P.mesh)
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")  # noqa: E731
+    bc = hbl.BC(to(P.dirichlet), P.outlet_h, P.outlet_R)
+    bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
+    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
+    hbl.newton_solve(gm, replace(prm, K=0), bc0, Ys,
+                     hbl.SolveOptions(rtol=1e-10, max_newton=30, max_gmres=300),
+                     raise_on_noconv=False)
+    Y0 = torch.zeros((4, N, n), dtype=torch.float64, device="cuda:0")
+    Y0[:, 0] = Ys[:, 0]
+    r0 = hbl.newton_solve(gm, prm, bc, Y0.clone(), hbl.SolveOptions(max_newton=0),
+                          raise_on_noconv=False)["r0"]
+    out = {"workload": workload, "n_nodes": n, "K": prm.K, "steps": steps, "runs": {}}
+    for cfl in cfls:
+        Y = Y0.clone()
+        opts = hbl.SolveOptions(rtol=1e-30, r_ref=r0, max_newton=1, max_gmres=300, cfl=cfl,
+                                cfl_max=cfl)
+        hist, gm_its = [], 0
+        torch.cuda.synchronize()
+        t = time.time()
+        for _ in range(steps):
+            try:
+                rep = hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False)
+            except hbl.HBError:
+                hist.append(float("nan"))
+                break
+            hist.append(rep["r_final"] / r0)
+            gm_its += rep["gmres_iters"]
+        torch.cuda.synchronize()
+        out["runs"][str(cfl)] = {"rel_residual": hist, "gmres_iters": gm_its,
+                                 "seconds": time.time() - t}
+        log(f"cfl {cfl}: residual after {len(hist)} steps {hist[-1]:.3e}, {gm_its} GMRES")
+    gm.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +329,8 @@ def main():
     ap.add_argument("--learned-train", type=int, default=384,
                     help="training solutions of the learned warm-start leg (0: skip it)")
     ap.add_argument("--learned-test", type=int, default=12)
+    ap.add_argument("--cfl-study", choices=["tjunction", "womersley"], default=None,
+                    help="fixed-pseudo-step CFL study on this workload (skips the main bench)")
     ap.add_argument("--branching", type=int, default=0,
                     help="Newton steps of the branching-artery leg (0: skip it; the mesh "
                          "takes about a minute to generate)")
@@ -290,6 +346,10 @@ def main():
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
+
+    if args.cfl_study:
+        print(json.dumps({"cfl_study": cfl_study(hbl, torch, log, args.cfl_study)}), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     t0 = time.time()

@@ -250,11 +250,13 @@ class WarmStart:
         return Y
 
 
-def compare_starts(model: WarmStart, case: Case, theta, rtol=1e-8, learned_max_newton=60):
+def compare_starts(model: WarmStart, case: Case, theta, rtol=1e-8, learned_max_newton=60,
+                   precision=HB_F64):
     """Plain start vs learned guess, both to the same absolute FP64 residual
-    rtol * ||r(plain start)||.  If Newton from the guess does not converge
-    within learned_max_newton steps (or breaks down), the plain start is
-    solved instead and both attempts are charged to the learned path."""
+    rtol * ||r(plain start)|| with the given Krylov precision.  If Newton from
+    the guess does not converge within learned_max_newton steps (or breaks
+    down), the plain start is solved instead and both attempts are charged
+    to the learned path."""
     import torch
     from . import HBError
     torch.cuda.synchronize()
@@ -271,7 +273,8 @@ def compare_starts(model: WarmStart, case: Case, theta, rtol=1e-8, learned_max_n
     Yl = Yg.clone()
     t0 = time.perf_counter()
     try:
-        rep_l = case.solve(Yl, r_plain, rtol, max_newton=learned_max_newton)
+        rep_l = case.solve(Yl, r_plain, rtol, max_newton=learned_max_newton,
+                           precision=precision)
     except HBError as e:         # non-finite residual on the way
         torch.cuda.synchronize()
         rep_l = dict(status=e.status, newton_iters=learned_max_newton, gmres_iters=0,
@@ -279,13 +282,13 @@ def compare_starts(model: WarmStart, case: Case, theta, rtol=1e-8, learned_max_n
     used = "learned"
     if rep_l["status"] != 0:
         Yl = Yp.clone()
-        rep_f = case.solve(Yl, r_plain, rtol)
+        rep_f = case.solve(Yl, r_plain, rtol, precision=precision)
         rep_l = dict(rep_f, newton_iters=rep_l["newton_iters"] + rep_f["newton_iters"],
                      gmres_iters=rep_l["gmres_iters"] + rep_f["gmres_iters"],
                      wall_s=rep_l["wall_s"] + rep_f["wall_s"])
         used = "plain"
     Y0 = Yp.clone()
-    rep_p = case.solve(Yp, r_plain, rtol)
+    rep_p = case.solve(Yp, r_plain, rtol, precision=precision)
     nrm = torch.linalg.norm(Yp)
 
     def err(Y):
