@@ -45,7 +45,7 @@ class _Opts(C.Structure):
                 ("cfl", C.c_double), ("c1", C.c_double), ("restart", C.c_int32),
                 ("max_newton", C.c_int32), ("max_gmres", C.c_int32), ("precision", C.c_int32),
                 ("jv_kind", C.c_int32), ("verbose", C.c_int32), ("precond", C.c_int32),
-                ("cfl_max", C.c_double)]
+                ("cfl_max", C.c_double), ("graphs", C.c_int32)]
 
 
 class _Report(C.Structure):
@@ -254,11 +254,12 @@ class SolveOptions:
     verbose: int = 0
     precond: int = HB_PREC_NODE_TIME
     cfl_max: float = 0.0
+    graphs: int = 0  # 1: replay captured Arnoldi steps (HIP graphs) at launch-bound sizes
 
     def _c(self):
         return _Opts(self.rtol, self.r_ref, self.gmres_eta, self.cfl, self.c1, self.restart,
                      self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose,
-                     self.precond, self.cfl_max)
+                     self.precond, self.cfl_max, self.graphs)
 
 
 def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None,

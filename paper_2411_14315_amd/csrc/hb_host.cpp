@@ -79,12 +79,25 @@ struct Workspace {
 // Krylov buffers kept on the mesh between solves, pinned host slots for the
 // Arnoldi coefficients, and events.
 struct SolverBufs {
-  DevBuf basis, xvec, rvec, tmp, partial, hdev, rbuf, uc;
+  DevBuf basis, xvec, rvec, tmp, partial, hdev, rbuf, uc, shift;
   double* hpin = nullptr;  // pinned host copies of each Arnoldi step's coefficients
   size_t hpin_n = 0;
   hipEvent_t evh[2] = {};  // Arnoldi step completion (ping-pong)
   hipEvent_t evj[4] = {};  // Jv timing: two (start, end) pairs
+  // Arnoldi steps captured as HIP graphs, one per step index, valid while
+  // every pointer and size they were captured with (key) is unchanged.
+  std::vector<uintptr_t> gkey;
+  std::vector<hipGraphExec_t> gexec;
+  hipStream_t gstream = nullptr;  // private stream used only for capture
+  void drop_graphs() {
+    for (auto& e : gexec)
+      if (e) (void)hipGraphExecDestroy(e);
+    gexec.clear();
+    gkey.clear();
+  }
   ~SolverBufs() {
+    drop_graphs();
+    if (gstream) (void)hipStreamDestroy(gstream);
     if (hpin) (void)hipHostFree(hpin);
     for (auto& e : evh)
       if (e) (void)hipEventDestroy(e);
@@ -122,7 +135,7 @@ struct hb_mesh {
     for (const DevBuf* d : {&tets, &geo, &dmask, &of, &ofn, &oid, &mass, &inlet_dev, &ws.Sy, &ws.Sv,
                             &ws.acc, &ws.tab, &ws.small, &ws.dg, &ws.dinv, &ws.binv, &ws.Sy32,
                             &ws.Sv32, &ws.acc32, &sb.basis, &sb.xvec, &sb.rvec, &sb.tmp,
-                            &sb.partial, &sb.hdev, &sb.rbuf, &sb.uc})
+                            &sb.partial, &sb.hdev, &sb.rbuf, &sb.uc, &sb.shift})
       b += d->bytes;
     for (const auto& bm : bmaps) b += bm.ptr.bytes + bm.nodes.bytes + bm.slot.bytes;
     return b;
@@ -188,6 +201,7 @@ Phys make_phys(const hb_params* prm, double shift) {
   p.beta = prm->beta_bf;
   p.omega = 6.283185307179586476925286766559 / prm->period;
   p.shift = shift;
+  p.shift_dev = nullptr;
   p.N = 2 * prm->K + 1;
   p.backflow = prm->beta_bf > 0 ? 1 : 0;
   return p;
@@ -744,6 +758,9 @@ struct Solver {
   int jv_kind;
   const double* binv = nullptr;  // per-node time blocks, or NULL for the diagonal
   bool jv64 = false;  // FP32 basis with FP64 Jacobian-vector products (HB_F32_BASIS)
+  bool use_graphs = false;     // replay captured Arnoldi steps
+  bool timed_apply = true;     // false while capturing
+  const double* shift_dev = nullptr;
   SolverBufs* sb = nullptr;
   double jv_ms = 0.0;
   int n_jv = 0;
@@ -774,13 +791,15 @@ struct Solver {
                                 std::max<size_t>((size_t)(restart + 2) * nblk, kNormBlocks)));
     HB_CHECK(sb->hdev.ensure(sizeof(double) * (4 * (size_t)(restart + 1) + 8)));
     const size_t slot = 2 * (size_t)(restart + 1) + 1;
-    if (sb->hpin_n < slot * restart) {
+    if (sb->hpin_n < slot * restart + 1) {  // + one slot for the pseudo-time shift
       if (sb->hpin) HB_CHECK(hipHostFree(sb->hpin));
       sb->hpin = nullptr;
       sb->hpin_n = 0;
-      HB_CHECK(hipHostMalloc((void**)&sb->hpin, sizeof(double) * slot * restart));
-      sb->hpin_n = slot * restart;
+      HB_CHECK(hipHostMalloc((void**)&sb->hpin, sizeof(double) * (slot * restart + 1)));
+      sb->hpin_n = slot * restart + 1;
     }
+    HB_CHECK(sb->shift.ensure(sizeof(double)));
+    if (use_graphs && !sb->gstream) HB_CHECK(hipStreamCreateWithFlags(&sb->gstream, hipStreamNonBlocking));
     for (auto& e : sb->evh)
       if (!e) HB_CHECK(hipEventCreate(&e));
     for (auto& e : sb->evj)
@@ -835,18 +854,18 @@ struct Solver {
     Workspace& w = m->ws;
     Ptrs s = small_ptrs(m);
     const double* tab = w.tab.as<double>();
-    const Phys p = make_phys(prm, shift);
+    Phys p = make_phys(prm, shift);
+    p.shift_dev = shift_dev;
     if constexpr (!std::is_same<T, double>::value) {
       if (jv64) return apply_f64(q, wout, p, s, tab);
     }
     T* Sv = dir();
     T* acc = accum();
     const int pr = n_jv & 1;
-    if (jv_pending[pr]) {
-      int rc = collect_jv(pr);
+    if (timed_apply) {
+      int rc = timer_start(pr);
       if (rc) return rc;
     }
-    HB_CHECK(hipEventRecord(sb->evj[2 * pr], st));
     HB_CHECK(hb::prepare_direction<T, T>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab, Sv,
                                          acc, s.dQ, m->dm.n_out * N, st));
     if (jv_kind == HB_JV_EXACT) {
@@ -863,6 +882,20 @@ struct Solver {
         return fail(HB_ERR_ARG, "the paper tangent is available in FP64 only");
       }
     }
+    return timed_apply ? timer_stop(pr) : HB_OK;
+  }
+
+  // Jv timing with two event pairs used in turn; a pair's previous
+  // duration is collected (waited for) before the pair is reused.
+  int timer_start(int pr) {
+    if (jv_pending[pr]) {
+      int rc = collect_jv(pr);
+      if (rc) return rc;
+    }
+    HB_CHECK(hipEventRecord(sb->evj[2 * pr], st));
+    return HB_OK;
+  }
+  int timer_stop(int pr) {
     HB_CHECK(hipEventRecord(sb->evj[2 * pr + 1], st));
     jv_pending[pr] = true;
     ++n_jv;
@@ -876,11 +909,10 @@ struct Solver {
     double* Sv = w.Sv.as<double>();
     double* acc = w.acc.as<double>();
     const int pr = n_jv & 1;
-    if (jv_pending[pr]) {
-      int rc = collect_jv(pr);
+    if (timed_apply) {
+      int rc = timer_start(pr);
       if (rc) return rc;
     }
-    HB_CHECK(hipEventRecord(sb->evj[2 * pr], st));
     HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab,
                                                 Sv, acc, s.dQ, m->dm.n_out * N, st)));
     if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, Sv, s.dQ, st));
@@ -888,10 +920,27 @@ struct Solver {
                                         pick_blocks(m, N), st));
     HB_CHECK(hb::face_jvp<double>(m->dm, p, w.Sy.as<double>(), Sv, s.R, s.dQ, acc, st));
     HB_CHECK((hb::finish_rows<double, T>(m->dm, N, acc, 1, tab, q, wout, st)));
-    HB_CHECK(hipEventRecord(sb->evj[2 * pr + 1], st));
-    jv_pending[pr] = true;
-    ++n_jv;
-    return HB_OK;
+    return timed_apply ? timer_stop(pr) : HB_OK;
+  }
+
+  // Everything a captured Arnoldi step depends on by value: sizes, device
+  // pointers and the fluid parameters baked into its kernel arguments.
+  std::vector<uintptr_t> graph_key() {
+    Workspace& w = m->ws;
+    const Ptrs s = small_ptrs(m);
+    auto bits = [](double v) {
+      uint64_t u;
+      std::memcpy(&u, &v, sizeof(u));
+      return (uintptr_t)u;
+    };
+    return {(uintptr_t)N, (uintptr_t)restart, (uintptr_t)L, (uintptr_t)nblk,
+            (uintptr_t)jv_kind, (uintptr_t)jv64, (uintptr_t)sizeof(T),
+            (uintptr_t)sb->basis.p, (uintptr_t)sb->partial.p, (uintptr_t)sb->hdev.p,
+            (uintptr_t)sb->shift.p, (uintptr_t)binv, (uintptr_t)w.dinv.p, (uintptr_t)w.tab.p,
+            (uintptr_t)w.small.p, (uintptr_t)s.R, (uintptr_t)w.Sy.p, (uintptr_t)w.Sv.p,
+            (uintptr_t)w.acc.p, (uintptr_t)w.Sy32.p, (uintptr_t)w.Sv32.p, (uintptr_t)w.acc32.p,
+            (uintptr_t)pick_blocks(m, N).ptr, bits(prm->rho), bits(prm->mu), bits(prm->period),
+            bits(prm->C_I), bits(prm->beta_bf)};
   }
 
   // Adds the duration of a recorded Jv (waits for it).
@@ -939,8 +988,22 @@ struct Solver {
     double* h2 = h1 + (mr + 1);
     double* h3 = h2 + (mr + 1);
     double* ydev = h1 + slot;
-    // queue Arnoldi step j: w = A v_j, two Gram-Schmidt passes, |w|^2, normalise
-    auto enqueue = [&](int j) -> int {
+    if (use_graphs) {
+      // the shift is read from device memory, so captured steps stay valid
+      sb->hpin[slot * mr] = shift;
+      HB_CHECK(hipMemcpyAsync(sb->shift.p, sb->hpin + slot * mr, sizeof(double),
+                              hipMemcpyHostToDevice, st));
+      shift_dev = sb->shift.as<double>();
+      const std::vector<uintptr_t> key = graph_key();
+      if (key != sb->gkey) {
+        sb->drop_graphs();
+        sb->gkey = key;
+      }
+      if ((int)sb->gexec.size() < mr) sb->gexec.resize(mr, nullptr);
+    }
+    // kernels of Arnoldi step j: w = A v_j, two Gram-Schmidt passes, |w|^2,
+    // normalisation (no host work in between, so the sequence can be captured)
+    auto step_kernels = [&](int j) -> int {
       T* wj = Q(j + 1);
       int rc2 = apply(Q(j), wj, shift);
       if (rc2) return rc2;
@@ -950,6 +1013,49 @@ struct Solver {
       HB_CHECK(hb::vec_mdots<T>(Q(0), L, j + 1, wj, L, part, nblk, h2, st));
       HB_CHECK(hb::vec_axpy_norm<T>(wj, Q(0), L, j + 1, h2, L, part, kNormBlocks, h3, st));
       HB_CHECK(hb::vec_scale_inv_norm<T>(wj, L, h3, st));
+      return HB_OK;
+    };
+    // capture step j on the private stream (nothing runs during capture)
+    auto capture = [&](int j) -> int {
+      hipStream_t saved = st;
+      st = sb->gstream;
+      timed_apply = false;
+      hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      const int rc2 = e == hipSuccess ? step_kernels(j) : HB_OK;
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(st, &g) : e;
+      st = saved;
+      timed_apply = true;
+      if (rc2 != HB_OK || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc2 != HB_OK) return rc2;
+        return fail(HB_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
+      }
+      const hipError_t e3 = hipGraphInstantiate(&sb->gexec[j], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e3 != hipSuccess) {
+        sb->gexec[j] = nullptr;
+        return fail(HB_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e3));
+      }
+      return HB_OK;
+    };
+    // queue Arnoldi step j and the copy of its coefficients to the host
+    auto enqueue = [&](int j) -> int {
+      if (use_graphs) {
+        if (!sb->gexec[j]) {
+          const int rc2 = capture(j);
+          if (rc2) return rc2;
+        }
+        const int pr = n_jv & 1;
+        int rc2 = timer_start(pr);
+        if (rc2) return rc2;
+        HB_CHECK(hipGraphLaunch(sb->gexec[j], st));
+        rc2 = timer_stop(pr);
+        if (rc2) return rc2;
+      } else {
+        const int rc2 = step_kernels(j);
+        if (rc2) return rc2;
+      }
       HB_CHECK(hipMemcpyAsync(sb->hpin + (size_t)j * slot, h1, sizeof(double) * slot,
                               hipMemcpyDeviceToHost, st));
       HB_CHECK(hipEventRecord(sb->evh[j & 1], st));
@@ -1057,6 +1163,8 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   S.nblk = 1024;  // workgroups per vector slice of the Krylov reductions (upper bound)
   S.jv_kind = opts->jv_kind == HB_JV_PAPER ? HB_JV_PAPER : HB_JV_EXACT;
   S.jv64 = opts->precision == HB_F32_BASIS;
+  // on request, launch-bound sizes replay captured Arnoldi steps
+  S.use_graphs = opts->graphs == 1 && S.L <= ((int64_t)1 << 22) && S.jv_kind == HB_JV_EXACT;
   const int N = S.N;
   const int64_t L = S.L;
   int rc = S.alloc();

@@ -52,6 +52,8 @@ struct Phys {
   double rho, mu, nu, C_I, beta, omega;
   double inv_rho;    // 1 / rho
   double shift;      // pseudo-time mass coefficient on velocity rows (0 = none)
+  const double* shift_dev;  // if set, the exact-Jv kernel reads the shift here instead
+                            // (replayed graphs stay valid when the shift changes)
   int32_t N;
   int32_t backflow;  // 1 = backflow term on outlets
 };

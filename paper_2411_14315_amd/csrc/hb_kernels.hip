@@ -812,7 +812,7 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
   }
   quad_gather_rows(cr, res);
   const R V = G.V;
-  const R ms = R(p.shift) * V * R(1.0 / 20.0);
+  const R ms = R(p.shift_dev ? *p.shift_dev : p.shift) * V * R(1.0 / 20.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     res[i] += V * (R(p.mu) * (gA[0] * dG[i][0] + gA[1] * dG[i][1] + gA[2] * dG[i][2]) - gA[i] * dpbar)

@@ -266,3 +266,35 @@ def test_mixed_solve_matches_oracle_solution(c1, precision):
                                             precision=prec))
     assert rep["status"] == 0
     assert rel(host(Y), g["Y"]) <= TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager(c1, precision):
+    """Arnoldi steps replayed from captured HIP graphs (graphs = 1) against
+    eager launches: five Newton steps, each taken from the same
+    state by two eager runs and one graph run.  The graph run agrees with the
+    eager one as closely as two eager runs agree with each other (hardware
+    atomics make the sums' order, hence the rounding, vary from run to run),
+    and takes the same GMRES iterations.  The graphs captured in the first
+    step are replayed in the later ones with a different pseudo-time shift."""
+    g = np.load(os.path.join(HERE, "golden", "c1_solution.npz"))
+    P = c1.P
+    prec = hbl.HB_MIXED if precision == "mixed" else hbl.HB_F64
+    Y = dev(g["Y0"])
+    r_ref = hbl.newton_solve(c1.gm, P.params, c1.bc, Y.clone(),
+                             hbl.SolveOptions(max_newton=0), raise_on_noconv=False)["r0"]
+    for step in range(5):
+        out = []
+        for mode in (0, 0, 1):
+            Yk = Y.clone()
+            rep = hbl.newton_solve(c1.gm, P.params, c1.bc, Yk,
+                                   hbl.SolveOptions(rtol=1e-30, r_ref=r_ref, max_newton=1,
+                                                    max_gmres=100, precision=prec, graphs=mode),
+                                   raise_on_noconv=False)
+            out.append((rep, host(Yk)))
+        spread = rel(out[1][1], out[0][1])
+        diff = rel(out[2][1], out[0][1])
+        print(precision, step, "eager spread", spread, "graph vs eager", diff, flush=True)
+        assert out[2][0]["gmres_iters"] == out[0][0]["gmres_iters"]
+        assert diff <= max(1e-12, 10.0 * spread), step
+        Y = dev(out[2][1])
