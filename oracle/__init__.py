@@ -13,4 +13,4 @@ complex-step derivative is taken).  Each module cites the passage it follows.
 Parity status: every function is pinned by a test under ``tests/`` (closed
 forms, identities, brute force); see ``tests/test_oracle_*.py``.
 """
-from . import spectral, fem, residual, tangent, api, solve  # noqa: F401
+from . import spectral, fem, residual, tangent, api, solve, march  # noqa: F401

@@ -44,6 +44,8 @@ class Options:
     backflow: bool = True
     frozen_u: np.ndarray | None = None     # (3, N, n) advecting velocity (Picard-frozen form)
     body_force: np.ndarray | None = None   # (3, N, n) nodal samples of f (manufactured tests)
+    stab_test_time: bool = True   # the -H N_A part of the momentum test operator (HB only)
+    tau_add: float = 0.0          # added inside tau's bracket (omega-hat^2 of eq. tauhat)
 
 
 def _scatter(target: np.ndarray, idx: np.ndarray, vals: np.ndarray):
@@ -149,7 +151,7 @@ def residual_samples(om: OMesh, prm, y: np.ndarray, h_samples: np.ndarray,
             uq = np.einsum("a,enai->eni", Nq, UB)
             hq = np.einsum("a,enai->eni", Nq, HU)
             fq = np.einsum("a,enai->eni", Nq, FB) if FB is not None else 0.0
-            kap = prm.C_I * nu * nu * xixi[:, None]
+            kap = prm.C_I * nu * nu * xixi[:, None] + opt.tau_add
             if opt.convection:
                 adv = np.einsum("enj,enij->eni", uq, G)
                 kap = kap + np.einsum("eni,eij,enj->en", uq, xi, uq)
@@ -196,7 +198,7 @@ def residual_samples(om: OMesh, prm, y: np.ndarray, h_samples: np.ndarray,
                 bf += coef[:, :, None, None] * Nq[None, None, :, None] * uq[:, :, None, :]
             _scatter_vec(rm, of, bf)
 
-    if opt.stab_time_terms:
+    if opt.stab_time_terms and opt.stab_test_time:
         rm -= np.einsum("nk,ika->ina", H, z)
     rm[:, :, om.dirichlet] = 0.0
     out = np.empty((4, N, n), dtype=dt)
@@ -211,9 +213,11 @@ def jvp_samples(om: OMesh, prm, y: np.ndarray, v: np.ndarray, h_samples: np.ndar
     """Exact directional derivative d r(y)[v] written out term by term
     (tangent-linear of residual_samples).  v's Dirichlet velocity samples are
     treated as zero.  ``shift`` adds shift * int N_A N_B v_B,i on velocity
-    rows (the pseudo-time term of Section 2.3)."""
+    rows (the pseudo-time term of Section 2.3).  A body force is constant in
+    y: it enters only through the strong residual L that d tau and the
+    perturbed advective test function multiply."""
     opt = opt or Options()
-    if opt.frozen_u is not None or opt.body_force is not None:
+    if opt.frozen_u is not None:
         raise ValueError("jvp_samples takes the plain residual only")
     rho, mu = prm.rho, prm.mu
     nu = mu / rho
@@ -236,6 +240,7 @@ def jvp_samples(om: OMesh, prm, y: np.ndarray, v: np.ndarray, h_samples: np.ndar
         HU, dHU = _gather(Hu, idx), _gather(dHu, idx)
         P = y[3][:, idx].transpose(1, 0, 2)
         dP = v[3][:, idx].transpose(1, 0, 2)
+        FB = _gather(opt.body_force, idx) if opt.body_force is not None else None
         G = np.einsum("enai,eaj->enij", U, gr)
         dG = np.einsum("enai,eaj->enij", dU, gr)
         g = np.einsum("ena,eai->eni", P, gr)
@@ -253,7 +258,8 @@ def jvp_samples(om: OMesh, prm, y: np.ndarray, v: np.ndarray, h_samples: np.ndar
             duq = np.einsum("a,enai->eni", Nq, dU)
             hq = np.einsum("a,enai->eni", Nq, HU)
             dhq = np.einsum("a,enai->eni", Nq, dHU)
-            kap = prm.C_I * nu * nu * xixi[:, None]
+            fq = np.einsum("a,enai->eni", Nq, FB) if FB is not None else 0.0
+            kap = prm.C_I * nu * nu * xixi[:, None] + opt.tau_add
             if opt.convection:
                 adv = np.einsum("enj,enij->eni", uq, G)
                 dadv = np.einsum("enj,enij->eni", duq, G) + np.einsum("enj,enij->eni", uq, dG)
@@ -268,7 +274,7 @@ def jvp_samples(om: OMesh, prm, y: np.ndarray, v: np.ndarray, h_samples: np.ndar
                 cA = dcA = None
             tau = kap ** -0.5
             dtau = -tau ** 3 * dkap_half
-            L = rho * (st * hq + adv) + g
+            L = rho * (st * hq + adv - fq) + g
             dL = rho * (st * dhq + dadv) + dg
             s = tau[:, :, None] * L
             ds = (dtau[:, :, None] * L if opt.convection else 0.0) + tau[:, :, None] * dL
@@ -314,7 +320,7 @@ def jvp_samples(om: OMesh, prm, y: np.ndarray, v: np.ndarray, h_samples: np.ndar
                 bf += (coef * dterm)[:, :, None, :] * Nq[None, None, :, None]
             _scatter_vec(rm, of, bf)
 
-    if opt.stab_time_terms:
+    if opt.stab_time_terms and opt.stab_test_time:
         rm -= np.einsum("nk,ika->ina", H, z)
     rm[:, :, om.dirichlet] = 0.0
     out = np.empty((4, N, n))
