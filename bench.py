@@ -20,6 +20,8 @@ The line reports:
                operator time from HIP events on the solve stream;
   ms_per_step  wall time per Newton step;
   jv_public    throughput of the public modal hb_jvp entry point;
+  tm_step_jv   one time-marching step's exact Jv (hb_tm_jvp) on the same
+               mesh, and how many of them one HB Jv costs;
   time_to_1e8  a complete FP64 solve to 1e-8 of the Womersley-pipe workload
                (1,911 nodes, K = 2) from its plain start;
   roofline     the element Jacobian-vector kernel against the FP64 vector
@@ -54,7 +56,7 @@ ELEM_FLOPS = {"exact": 1680, "paper": 970, "residual": 1040}
 # size, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) counters,
 # each scale read off a plain 1 GiB device copy; valid while the
 # element-kernel source section hashes to the recorded value.
-ELEM_TRAFFIC = {"sha256_prefix": "d15e4ce20664828d", "fetch_kib": 394044, "write_kib": 1193487,
+ELEM_TRAFFIC = {"sha256_prefix": "00647bcc99c7fb0f", "fetch_kib": 394028, "write_kib": 1193487,
                 "fetch_scale": 2.0, "write_scale": 1.0, "n_nodes": 158688, "n_tets": 848252,
                 "K": 10, "profile": "profiles/k_elem_jvp_exact_tjunction_K10_traffic.md"}
 
@@ -110,6 +112,33 @@ def cpu_baseline(P, Y, V, budget_s=30.0):
             "kind": "oracle",
             "sample": f"exact Jv rows of {rows.size} nodes ({nel} of {om.ne} tetrahedra, "
                       f"{dt:.1f} s), scaled by element count"}
+
+
+def tm_step_jv(hbl, torch, P, gm, Y0, V, st, reps):
+    """Exact Jv of one time-marching step (hb_tm_jvp: one time level, the
+    mean modes of the HB state and direction as the step's state and
+    direction, dt = T/200, omega-hat = 2 pi / T) on the same mesh, timed
+    with HIP events on the launch stream."""
+    n = P.mesh.n_nodes
+    y = Y0[:, 0].contiguous()
+    v = V[:, 0].contiguous()
+    a_old = torch.zeros((3, n), dtype=torch.float64, device="cuda:0")
+    g = torch.from_numpy(np.ascontiguousarray(P.dirichlet[:, 0])).to("cuda:0")
+    h = np.ascontiguousarray(P.outlet_h[:, 0])
+    tm = hbl.TmStep(P.params.period / 200, 2 * np.pi / P.params.period, y.clone(), a_old, g, h,
+                    P.outlet_R)
+    jv = torch.empty_like(v)
+    for _ in range(5):
+        hbl.tm_jvp(gm, P.params, tm, y, v, jv)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        hbl.tm_jvp(gm, P.params, tm, y, v, jv)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"ms": ms, "value": 4 * n / (ms * 1e-3) / 1e9, "unit": "GDOF/s"}
 
 
 def womersley_time_to_solution(hbl, torch, log, precision="fp64"):
@@ -426,6 +455,9 @@ def main():
     dofs = 4 * n * N
     jv_public = dofs / (tot * 1e-3) / 1e9
     log(f"hb_jvp: {tot:.3f} ms ({jv_public:.2f} GDOF-modes/s); stages {stages}")
+    tm_jv = tm_step_jv(hbl, torch, P, gm, Y0, V, st, args.jv_reps)
+    log(f"hb_tm_jvp (one time-marching step's Jv): {tm_jv['ms']:.3f} ms; "
+        f"HB Jv / step Jv = {tot / tm_jv['ms']:.1f}")
 
     elem_ms = stages["element"]
     flops = ELEM_FLOPS["exact"] * ne * N
@@ -498,6 +530,8 @@ def main():
                         "stages_ms": stages}
     out["jv_public_fp32"] = {"value": dofs / (tot32 * 1e-3) / 1e9, "unit": "GDOF-modes/s",
                              "ms": tot32, "stages_ms": stages32}
+    tm_jv["hb_jv_over_step_jv"] = tot / tm_jv["ms"]
+    out["tm_step_jv"] = tm_jv
     out["roofline"] = roofline
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, Y0.cpu().numpy(), V.cpu().numpy())

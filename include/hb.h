@@ -142,6 +142,75 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
 int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
               double shift, double* D, void* stream);
 
+/* One step of the GLS time-marching solver that Section 3 compares the HB
+ * solver with, at one time level (the K = 0 layout: arrays [f][n]).  The
+ * step solves r(u_{n+1}, p_{n+1}) = 0 with the Galerkin/least-squares terms
+ * of eq. Rmc, the acceleration a = (c1/dt)(u_{n+1} - u_n) + (1 - c1) a_n of
+ * the generalized-alpha method with rho_inf = 0 (c1 = 1.5, the c1 of
+ * Section 2.3) in place of H u, no time derivative on the test functions,
+ * and tau-hat of eq. tauhat: omega_hat^2 is added inside tau's bracket.
+ * prm->K and prm->period are not used.  All device arrays are caller-owned;
+ * y_old and a_old must not alias Y, R, V or JV. */
+typedef struct {
+  double dt;               /* time step > 0                                   */
+  double omega_hat;        /* ||du/dt|| / ||u|| of eq. tauhat, >= 0, held
+                              fixed over the step                             */
+  const double* y_old;     /* device [4][n] state at t_n (velocity rows read) */
+  const double* a_old;     /* device [3][n] acceleration at t_n               */
+  const double* dirichlet; /* device [3][n] Dirichlet velocity at t_{n+1}     */
+  const double* outlet_h;  /* host [n_outlets] traction at t_{n+1}, or NULL   */
+  const double* outlet_R;  /* host [n_outlets] resistance, or NULL            */
+} hb_tm_step;
+
+/* R = step residual at Y = (u_{n+1}, p_{n+1}) (device [4][n] in, [4][n]
+ * out; Y's Dirichlet velocity entries are replaced by tm->dirichlet;
+ * momentum rows at Dirichlet nodes are 0).  Asynchronous on the stream.
+ * HB_ERR_ARG for dt <= 0, a negative or non-finite omega_hat or a NULL
+ * required pointer. */
+int hb_tm_residual(const hb_mesh* mesh, const hb_params* prm, const hb_tm_step* tm,
+                   const double* Y, double* R, void* stream);
+
+/* JV = exact derivative of hb_tm_residual at Y along V (device [4][n];
+ * V's Dirichlet velocity entries are treated as 0).  Asynchronous. */
+int hb_tm_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_tm_step* tm, const double* Y,
+              const double* V, double* JV, void* stream);
+
+/* Options and report of hb_tm_march. */
+typedef struct {
+  double t0;          /* time of the initial state                          */
+  double dt;          /* time step > 0                                      */
+  int32_t n_steps;    /* steps to take, >= 0                                */
+  double rtol, atol;  /* a step converges when ||r|| <= max(atol, rtol ||r_0||)
+                         (2-norm of the step residual, r_0 at the previous
+                         state with the new boundary data)                  */
+  double gmres_eta;   /* GMRES relative tolerance per Newton iteration      */
+  int32_t restart, max_newton, max_gmres;
+  double omega_hat;   /* < 0: omega-hat of eq. tauhat from each step's
+                         starting state (mass-weighted velocity norms);
+                         >= 0: held at this value                           */
+  int32_t verbose;    /* 1: one line per step on stderr                     */
+} hb_tm_opts;
+
+typedef struct {
+  int32_t steps, newton_iters, gmres_iters, status;
+  double max_step_residual, wall_s;
+} hb_tm_report;
+
+/* March the GLS comparison solver of Section 3 (the step of hb_tm_residual)
+ * over n_steps steps t0 + k dt with the boundary data of bc evaluated at
+ * each t_{k+1}: modal Dirichlet data (device [3][2K+1][n], prm->K and
+ * prm->period give the harmonics) and modal outlet traction (host).  Each
+ * step is solved by Newton-GMRES with the exact step Jacobian, right-
+ * preconditioned by the Jacobi diagonal of the paper's tangent plus
+ * 1.5 rho/dt times the mass diagonal.  Y (device [4][n]) and A (device
+ * [3][n]) hold the state and acceleration at t0 on entry and at the last
+ * step on return; traj (device [n_steps][4][n], or NULL) receives the
+ * state after every step.  Synchronous on return.  HB_ERR_NOCONV if a step
+ * reached max_newton (the march still completes), HB_ERR_NAN on a
+ * non-finite residual, HB_ERR_ARG for invalid options. */
+int hb_tm_march(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y, double* A,
+                double* traj, const hb_tm_opts* opts, hb_tm_report* report, void* stream);
+
 /* Preconditioners for hb_newton_solve.  HB_PREC_JACOBI is the paper's Jacobi
  * preconditioner diag(P) (Section 2.3).  HB_PREC_NODE_TIME keeps, for every
  * node, the full N x N time block of the exact Jacobian's velocity diagonal:

@@ -40,6 +40,24 @@ class _BC(C.Structure):
     _fields_ = [("dirichlet", C.c_void_p), ("outlet_h", C.c_void_p), ("outlet_R", C.c_void_p)]
 
 
+class _TmStep(C.Structure):
+    _fields_ = [("dt", C.c_double), ("omega_hat", C.c_double), ("y_old", C.c_void_p),
+                ("a_old", C.c_void_p), ("dirichlet", C.c_void_p), ("outlet_h", C.c_void_p),
+                ("outlet_R", C.c_void_p)]
+
+
+class _TmOpts(C.Structure):
+    _fields_ = [("t0", C.c_double), ("dt", C.c_double), ("n_steps", C.c_int32),
+                ("rtol", C.c_double), ("atol", C.c_double), ("gmres_eta", C.c_double),
+                ("restart", C.c_int32), ("max_newton", C.c_int32), ("max_gmres", C.c_int32),
+                ("omega_hat", C.c_double), ("verbose", C.c_int32)]
+
+
+class _TmReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("newton_iters", C.c_int32), ("gmres_iters", C.c_int32),
+                ("status", C.c_int32), ("max_step_residual", C.c_double), ("wall_s", C.c_double)]
+
+
 class _Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("r_ref", C.c_double), ("gmres_eta", C.c_double),
                 ("cfl", C.c_double), ("c1", C.c_double), ("restart", C.c_int32),
@@ -73,6 +91,10 @@ def load():
     lib.hb_residual.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, vp, vp]
     lib.hb_jvp.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, vp, vp, i32, vp]
     lib.hb_jacobi.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, dbl, vp, vp]
+    lib.hb_tm_residual.argtypes = [vp, C.POINTER(_Params), C.POINTER(_TmStep), vp, vp, vp]
+    lib.hb_tm_jvp.argtypes = [vp, C.POINTER(_Params), C.POINTER(_TmStep), vp, vp, vp, vp]
+    lib.hb_tm_march.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, vp, vp,
+                                C.POINTER(_TmOpts), C.POINTER(_TmReport), vp]
     lib.hb_newton_solve.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp,
                                     C.POINTER(_Opts), C.POINTER(_Report), vp]
     lib.hb_set_timing.argtypes = [vp, i32]
@@ -90,7 +112,8 @@ def load():
     for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
                  "hb_newton_solve", "hb_set_timing", "hb_last_timings", "hb_mlp_create",
                  "hb_mlp_num_params", "hb_mlp_get_params", "hb_mlp_forward", "hb_mlp_loss_grad",
-                 "hb_mlp_adam_step", "hb_pod_expand"):
+                 "hb_mlp_adam_step", "hb_pod_expand", "hb_tm_residual", "hb_tm_jvp",
+                 "hb_tm_march"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -226,6 +249,81 @@ def jvp(mesh: Mesh, params, bc: BC, Y, V, JV=None, kind: str = "exact", stream=N
     _check(load().hb_jvp(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), _ptr(V), _ptr(JV), flags,
                          _stream(stream)))
     return JV
+
+
+class TmStep:
+    """One time-marching step's data: ``y_old`` device (4, n) state at t_n,
+    ``a_old`` device (3, n) acceleration at t_n, ``dirichlet`` device (3, n)
+    Dirichlet velocity at t_{n+1}; ``outlet_h`` and ``outlet_R`` host
+    (n_outlets,) or None."""
+
+    def __init__(self, dt, omega_hat, y_old, a_old, dirichlet, outlet_h=None, outlet_R=None):
+        self.dt, self.omega_hat = float(dt), float(omega_hat)
+        self.y_old, self.a_old, self.dirichlet = y_old, a_old, dirichlet
+        self.outlet_h = None if outlet_h is None else np.ascontiguousarray(outlet_h, np.float64)
+        self.outlet_R = None if outlet_R is None else np.ascontiguousarray(outlet_R, np.float64)
+
+    def _c(self):
+        return _TmStep(self.dt, self.omega_hat, _ptr(self.y_old), _ptr(self.a_old),
+                       _ptr(self.dirichlet),
+                       None if self.outlet_h is None else self.outlet_h.ctypes.data,
+                       None if self.outlet_R is None else self.outlet_R.ctypes.data)
+
+
+def tm_residual(mesh: Mesh, params, tm: TmStep, Y, R=None, stream=None):
+    import torch
+    if R is None:
+        R = torch.empty_like(Y)
+    pc, tc = _params(params)._c(), tm._c()
+    _check(load().hb_tm_residual(mesh._h, C.byref(pc), C.byref(tc), _ptr(Y), _ptr(R),
+                                 _stream(stream)))
+    return R
+
+
+def tm_jvp(mesh: Mesh, params, tm: TmStep, Y, V, JV=None, stream=None):
+    import torch
+    if JV is None:
+        JV = torch.empty_like(V)
+    pc, tc = _params(params)._c(), tm._c()
+    _check(load().hb_tm_jvp(mesh._h, C.byref(pc), C.byref(tc), _ptr(Y), _ptr(V), _ptr(JV),
+                            _stream(stream)))
+    return JV
+
+
+@dataclass
+class TmOptions:
+    t0: float = 0.0
+    dt: float = 0.01
+    n_steps: int = 1
+    rtol: float = 1e-10
+    atol: float = 0.0
+    gmres_eta: float = 1e-6
+    restart: int = 50
+    max_newton: int = 20
+    max_gmres: int = 1000
+    omega_hat: float = -1.0  # < 0: eq. tauhat from each step's starting state
+    verbose: int = 0
+
+    def _c(self):
+        return _TmOpts(self.t0, self.dt, self.n_steps, self.rtol, self.atol, self.gmres_eta,
+                       self.restart, self.max_newton, self.max_gmres, self.omega_hat,
+                       self.verbose)
+
+
+def tm_march(mesh: Mesh, params, bc: BC, Y, A, opts: TmOptions, traj=None, stream=None,
+             raise_on_noconv: bool = True) -> dict:
+    """March in place: Y (4, n) and A (3, n) hold the state and acceleration
+    at opts.t0 on entry and after the last step on return; ``traj`` (a
+    device tensor (n_steps, 4, n)) or None receives every step's state."""
+    rep = _TmReport()
+    pc, bcc, oc = _params(params)._c(), bc._c(), opts._c()
+    st = load().hb_tm_march(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), _ptr(A),
+                            None if traj is None else _ptr(traj), C.byref(oc), C.byref(rep),
+                            _stream(stream))
+    out = {k: getattr(rep, k) for k, _ in _TmReport._fields_}
+    if st != HB_OK and not (st == HB_ERR_NOCONV and not raise_on_noconv):
+        _check(st)
+    return out
 
 
 def jacobi(mesh: Mesh, params, bc: BC, Y, shift: float = 0.0, D=None, stream=None):

@@ -122,6 +122,7 @@ struct hb_mesh {
   int device = 0;
   Workspace ws;
   SolverBufs sb;
+  DevBuf tm_yold, tm_g, tm_part;  // time marching: previous state, boundary data, norms
   // stage timing (hb_set_timing)
   bool timing = false;
   bool timed_call = false;
@@ -135,7 +136,8 @@ struct hb_mesh {
     for (const DevBuf* d : {&tets, &geo, &dmask, &of, &ofn, &oid, &mass, &inlet_dev, &ws.Sy, &ws.Sv,
                             &ws.acc, &ws.tab, &ws.small, &ws.dg, &ws.dinv, &ws.binv, &ws.Sy32,
                             &ws.Sv32, &ws.acc32, &sb.basis, &sb.xvec, &sb.rvec, &sb.tmp,
-                            &sb.partial, &sb.hdev, &sb.rbuf, &sb.uc, &sb.shift})
+                            &sb.partial, &sb.hdev, &sb.rbuf, &sb.uc, &sb.shift, &tm_yold, &tm_g,
+                            &tm_part})
       b += d->bytes;
     for (const auto& bm : bmaps) b += bm.ptr.bytes + bm.nodes.bytes + bm.slot.bytes;
     return b;
@@ -200,6 +202,7 @@ Phys make_phys(const hb_params* prm, double shift) {
   p.C_I = prm->C_I;
   p.beta = prm->beta_bf;
   p.omega = 6.283185307179586476925286766559 / prm->period;
+  p.tau_add = 0.0;
   p.shift = shift;
   p.shift_dev = nullptr;
   p.N = 2 * prm->K + 1;
@@ -711,6 +714,95 @@ int hb_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const dou
   return HB_OK;
 }
 
+// ------------------------------------------------------------ time marching
+// One step of the GLS time-marching solver (Section 3, eq. tauhat) at one
+// time level: the K = 0 pipeline with the time table's derivative entry
+// c1/dt (generalized-alpha, rho_inf = 0: c1 = alpha_m/gamma = 1.5), the
+// step history subtracted from the H u channels, no -H N_A test term and
+// omega-hat^2 inside tau's bracket.
+namespace {
+constexpr double kTmC1 = 1.5;
+
+int tm_prepare(hb_mesh* m, const hb_params* prm, const hb_tm_step* tm, hipStream_t st,
+               Phys& p) {
+  if (!tm) return fail(HB_ERR_ARG, "tm is NULL");
+  if (!(tm->dt > 0) || !std::isfinite(tm->dt)) return fail(HB_ERR_ARG, "dt must be positive");
+  if (!(tm->omega_hat >= 0) || !std::isfinite(tm->omega_hat))
+    return fail(HB_ERR_ARG, "omega_hat must be finite and >= 0");
+  if (!tm->y_old || !tm->a_old || !tm->dirichlet)
+    return fail(HB_ERR_ARG, "tm.y_old, tm.a_old and tm.dirichlet are required");
+  if (!prm) return fail(HB_ERR_ARG, "params is NULL");
+  hb_params p0 = *prm;
+  p0.K = 0;
+  const hb_bc bc0 = {tm->dirichlet, tm->outlet_h, tm->outlet_R};
+  int rc = prepare(m, &p0, &bc0, st);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  std::vector<double> tab(hb::TAB_COUNT, 0.0);
+  tab[hb::TAB_BINV] = 1.0;
+  tab[hb::TAB_BDER] = kTmC1 / tm->dt;
+  tab[hb::TAB_FWD] = 1.0;
+  tab[hb::TAB_H] = kTmC1 / tm->dt;
+  if (tab != w.tab_host) {
+    w.tab_host = tab;
+    HB_CHECK(hipMemcpyAsync(w.tab.p, w.tab_host.data(), sizeof(double) * tab.size(),
+                            hipMemcpyHostToDevice, st));
+  }
+  p = make_phys(&p0, 0.0);
+  p.tau_add = tm->omega_hat * tm->omega_hat;
+  return HB_OK;
+}
+}  // namespace
+
+int hb_tm_residual(const hb_mesh* mesh, const hb_params* prm, const hb_tm_step* tm,
+                   const double* Y, double* R, void* stream) {
+  if (!mesh || !Y || !R) return fail(HB_ERR_ARG, "NULL argument");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  Phys p;
+  int rc = tm_prepare(m, prm, tm, st, p);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  Ptrs s = small_ptrs(m);
+  const double* tab = w.tab.as<double>();
+  double* Sy = w.Sy.as<double>();
+  double* acc = w.acc.as<double>();
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, 1, Y, tm->dirichlet, 0, tab, Sy, acc, s.Q,
+                                                m->dm.n_out, st));
+  HB_CHECK(hb::tm_history(m->dm, Sy, tm->y_old, tm->a_old, kTmC1 / tm->dt, kTmC1 - 1.0, st));
+  if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, 1, Sy, s.Q, st));
+  HB_CHECK(hb::elem_residual(m->dm, p, Sy, acc, pick_blocks(m, 1), st));
+  HB_CHECK(hb::face_residual(m->dm, p, Sy, s.hs, s.R, s.Q, acc, st));
+  HB_CHECK(hb::samples_to_modal<double, double>(m->dm, 1, acc, 0, 1, hb::NCH, tab, R, st));
+  return HB_OK;
+}
+
+int hb_tm_jvp(const hb_mesh* mesh, const hb_params* prm, const hb_tm_step* tm, const double* Y,
+              const double* V, double* JV, void* stream) {
+  if (!mesh || !Y || !V || !JV) return fail(HB_ERR_ARG, "NULL argument");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  Phys p;
+  int rc = tm_prepare(m, prm, tm, st, p);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  Ptrs s = small_ptrs(m);
+  const double* tab = w.tab.as<double>();
+  double* Sy = w.Sy.as<double>();
+  double* Sv = w.Sv.as<double>();
+  double* acc = w.acc.as<double>();
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, 1, Y, tm->dirichlet, 0, tab, Sy, nullptr,
+                                                nullptr, 0, st));
+  HB_CHECK(hb::tm_history(m->dm, Sy, tm->y_old, tm->a_old, kTmC1 / tm->dt, kTmC1 - 1.0, st));
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, 1, V, tm->dirichlet, 1, tab, Sv, acc, s.dQ,
+                                                m->dm.n_out, st));
+  if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, 1, Sv, s.dQ, st));
+  HB_CHECK(hb::elem_jvp_exact<double>(m->dm, p, Sy, Sv, acc, pick_blocks(m, 1), st));
+  HB_CHECK(hb::face_jvp<double>(m->dm, p, Sy, Sv, s.R, s.dQ, acc, st));
+  HB_CHECK(hb::samples_to_modal<double, double>(m->dm, 1, acc, 0, 1, hb::NCH, tab, JV, st));
+  return HB_OK;
+}
+
 int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
               double shift, double* D, void* stream) {
   if (!mesh || !Y || !D) return fail(HB_ERR_ARG, "NULL argument");
@@ -762,6 +854,13 @@ struct Solver {
   bool timed_apply = true;     // false while capturing
   const double* shift_dev = nullptr;
   SolverBufs* sb = nullptr;
+  // time-marching step (hb_tm_march): tau-hat term, no -H z term, and the
+  // step history subtracted from the state's H u channels
+  double tau_add = 0.0;
+  int use_z = 1;
+  const double* hist_y = nullptr;
+  const double* hist_a = nullptr;
+  double hist_cu = 0.0, hist_ca = 0.0;
   double jv_ms = 0.0;
   int n_jv = 0;
   bool jv_pending[2] = {false, false};
@@ -824,16 +923,19 @@ struct Solver {
     Workspace& w = m->ws;
     Ptrs s = small_ptrs(m);
     const double* tab = w.tab.as<double>();
-    const Phys p = make_phys(prm, 0.0);
+    Phys p = make_phys(prm, 0.0);
+    p.tau_add = tau_add;
     double* Sy = w.Sy.as<double>();
     HB_CHECK(hb::prepare_direction<double, double>(m->dm, N, Sy, hb::NCH, nullptr, nullptr, 0,
                                                    tab, Sy, w.acc.as<double>(), s.Q,
                                                    m->dm.n_out * N, st));
+    if (hist_y)
+      HB_CHECK(hb::tm_history(m->dm, Sy, hist_y, hist_a, hist_cu, hist_ca, st));
     if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, Sy, s.Q, st));
     HB_CHECK(hb::elem_residual(m->dm, p, Sy, w.acc.as<double>(), pick_blocks(m, N), st));
     HB_CHECK(hb::face_residual(m->dm, p, Sy, s.hs, s.R, s.Q, w.acc.as<double>(), st));
-    HB_CHECK(hb::finish_rows<double, double>(m->dm, N, w.acc.as<double>(), 1, tab, nullptr, r,
-                                             st));
+    HB_CHECK(hb::finish_rows<double, double>(m->dm, N, w.acc.as<double>(), use_z, tab, nullptr,
+                                             r, st));
     int rc = sync_state();
     if (rc) return rc;
     return norm<double>(r, nrm);
@@ -856,6 +958,7 @@ struct Solver {
     const double* tab = w.tab.as<double>();
     Phys p = make_phys(prm, shift);
     p.shift_dev = shift_dev;
+    p.tau_add = tau_add;
     if constexpr (!std::is_same<T, double>::value) {
       if (jv64) return apply_f64(q, wout, p, s, tab);
     }
@@ -873,7 +976,7 @@ struct Solver {
       HB_CHECK(hb::elem_jvp_exact<T>(m->dm, p, state(), Sv, acc, pick_blocks(m, N),
                                      st));
       HB_CHECK(hb::face_jvp<T>(m->dm, p, state(), Sv, s.R, s.dQ, acc, st));
-      HB_CHECK(hb::finish_rows<T, T>(m->dm, N, acc, 1, tab, q, wout, st));
+      HB_CHECK(hb::finish_rows<T, T>(m->dm, N, acc, use_z, tab, q, wout, st));
     } else {
       if constexpr (std::is_same<T, double>::value) {
         HB_CHECK(hb::elem_jvp_paper(m->dm, p, w.Sy.as<double>(), Sv, acc, st));
@@ -919,7 +1022,7 @@ struct Solver {
     HB_CHECK(hb::elem_jvp_exact<double>(m->dm, p, w.Sy.as<double>(), Sv, acc,
                                         pick_blocks(m, N), st));
     HB_CHECK(hb::face_jvp<double>(m->dm, p, w.Sy.as<double>(), Sv, s.R, s.dQ, acc, st));
-    HB_CHECK((hb::finish_rows<double, T>(m->dm, N, acc, 1, tab, q, wout, st)));
+    HB_CHECK((hb::finish_rows<double, T>(m->dm, N, acc, use_z, tab, q, wout, st)));
     return timed_apply ? timer_stop(pr) : HB_OK;
   }
 
@@ -1259,9 +1362,150 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   return HB_OK;
 }
 
+// Time marching of the GLS comparison solver: n_steps generalized-alpha
+// steps, each solved by Newton-GMRES on the step residual with its exact
+// Jacobian (right-preconditioned by the Jacobi diagonal of the paper's
+// tangent plus c1 rho/dt times the mass diagonal).
+int tm_march_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y, double* A,
+                 double* traj, const hb_tm_opts* o, hb_tm_report* rep, hipStream_t st,
+                 std::chrono::steady_clock::time_point t0) {
+  const int64_t n = m->dm.n;
+  const int nout = m->dm.n_out;
+  const int Nb = 2 * prm->K + 1;
+  const double omega = 6.283185307179586476925286766559 / prm->period;
+  const double dt = o->dt;
+  HB_CHECK(m->tm_yold.ensure(sizeof(double) * 4 * n));
+  HB_CHECK(m->tm_g.ensure(sizeof(double) * 3 * n));
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+  HB_CHECK(m->tm_part.ensure(sizeof(double) * (2 * (size_t)nb + 2)));
+  double* yold = m->tm_yold.as<double>();
+  double* g = m->tm_g.as<double>();
+  double* part = m->tm_part.as<double>();
+  double* sums = part + 2 * nb;
+  hb_params p0 = *prm;
+  p0.K = 0;
+  std::vector<double> hstep(nout > 0 ? nout : 1, 0.0);
+  Solver<double> S;
+  S.m = m;
+  S.prm = &p0;
+  S.st = st;
+  S.N = 1;
+  S.L = 4 * n;
+  S.restart = o->restart;
+  S.nblk = 1024;
+  S.jv_kind = HB_JV_EXACT;
+  S.use_z = 0;
+  bool allocated = false;
+  int status = HB_OK;
+  for (int k = 0; k < o->n_steps; ++k) {
+    const double t1 = o->t0 + (double)(k + 1) * dt;
+    double what = o->omega_hat;
+    if (what < 0) {  // eq. tauhat from the step's starting state
+      HB_CHECK(hb::tm_norms(m->dm, Y, A, part, nb, sums, st));
+      double hs2[2] = {0.0, 0.0};
+      HB_CHECK(hipMemcpyAsync(hs2, sums, sizeof(hs2), hipMemcpyDeviceToHost, st));
+      HB_CHECK(hipStreamSynchronize(st));
+      what = hs2[0] > 0 ? std::sqrt(hs2[1] / hs2[0]) : 0.0;
+    }
+    HB_CHECK(hb::modal_eval(m->dm, prm->K, omega, t1, bc->dirichlet, g, st));
+    if (bc->outlet_h)
+      for (int q = 0; q < nout; ++q) {
+        const double* hq = bc->outlet_h + (size_t)q * Nb;
+        double v = hq[0];
+        for (int j = 1; j <= prm->K; ++j)
+          v += std::cos(j * omega * t1) * hq[2 * j - 1] + std::sin(j * omega * t1) * hq[2 * j];
+        hstep[q] = v;
+      }
+    HB_CHECK(hipMemcpyAsync(yold, Y, sizeof(double) * 4 * n, hipMemcpyDeviceToDevice, st));
+    const hb_tm_step tm = {dt, what, yold, A, g, bc->outlet_h ? hstep.data() : nullptr,
+                           bc->outlet_R};
+    Phys pp;
+    int rc = tm_prepare(m, prm, &tm, st, pp);
+    if (rc) return rc;
+    if (!allocated) {
+      rc = S.alloc();
+      if (rc) return rc;
+      HB_CHECK(m->sb.rbuf.ensure(sizeof(double) * S.L));
+      allocated = true;
+    }
+    S.tau_add = pp.tau_add;
+    S.hist_y = yold;
+    S.hist_a = A;
+    S.hist_cu = kTmC1 / dt;
+    S.hist_ca = kTmC1 - 1.0;
+    Workspace& w = m->ws;
+    const double* tab = w.tab.as<double>();
+    HB_CHECK(hb::modal_to_samples<double, double>(m->dm, 1, Y, g, 0, tab, w.Sy.as<double>(),
+                                                  nullptr, nullptr, 0, st));
+    double* r = m->sb.rbuf.as<double>();
+    double rn = 0.0;
+    rc = S.residual(r, rn);
+    if (rc) return rc;
+    if (!std::isfinite(rn)) return fail(HB_ERR_NAN, "non-finite step residual");
+    const double target = std::max(o->atol, o->rtol * rn);
+    int it = 0;
+    while (rn > target && it < o->max_newton) {
+      Phys pj = make_phys(&p0, prm->rho * kTmC1 / dt);
+      pj.tau_add = pp.tau_add;
+      HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), n * 2, st));
+      HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), 0, st));
+      HB_CHECK(hb::jacobi_out(m->dm, 1, 2, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
+      int gi = 0;
+      rc = S.gmres(r, 0.0, o->gmres_eta, o->max_gmres, gi);
+      if (rc) return rc;
+      rep->gmres_iters += gi;
+      rc = S.update_state();
+      if (rc) return rc;
+      rc = S.residual(r, rn);
+      if (rc) return rc;
+      if (!std::isfinite(rn)) return fail(HB_ERR_NAN, "non-finite step residual");
+      ++it;
+    }
+    rep->newton_iters += it;
+    rep->max_step_residual = std::max(rep->max_step_residual, rn);
+    if (rn > target) status = HB_ERR_NOCONV;
+    HB_CHECK(hb::samples_to_modal<double, double>(m->dm, 1, w.Sy.as<double>(), 0, 0, hb::NCH, tab,
+                                                  Y, st));
+    HB_CHECK(hb::tm_accel(m->dm, Y, yold, A, 1.0 / dt, st));
+    if (traj)
+      HB_CHECK(hipMemcpyAsync(traj + (size_t)k * 4 * n, Y, sizeof(double) * 4 * n,
+                              hipMemcpyDeviceToDevice, st));
+    rep->steps = k + 1;
+    if (o->verbose)
+      std::fprintf(stderr, "hb tm step %d: t %.4f newton %d |r| %.3e omega_hat %.3e\n", k + 1, t1,
+                   it, rn, what);
+  }
+  HB_CHECK(hipStreamSynchronize(st));
+  rep->status = status;
+  rep->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (status != HB_OK) return fail(status, "a step reached its Newton iteration limit");
+  return HB_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int hb_tm_march(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y, double* A,
+                double* traj, const hb_tm_opts* opts, hb_tm_report* report, void* stream) {
+  if (!mesh || !prm || !bc || !Y || !A || !opts || !report) return fail(HB_ERR_ARG, "NULL argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  std::memset(report, 0, sizeof(*report));
+  report->status = HB_ERR_NOCONV;
+  int rc = check_params(prm);
+  if (rc) return rc;
+  if (!bc->dirichlet) return fail(HB_ERR_ARG, "bc.dirichlet is NULL");
+  if (!(opts->dt > 0) || !std::isfinite(opts->dt) || !std::isfinite(opts->t0))
+    return fail(HB_ERR_ARG, "dt must be positive and t0 finite");
+  if (opts->n_steps < 0) return fail(HB_ERR_ARG, "n_steps must be >= 0");
+  if (!(opts->rtol > 0) || !(opts->atol >= 0) || !(opts->gmres_eta > 0))
+    return fail(HB_ERR_ARG, "rtol and gmres_eta must be positive, atol >= 0");
+  if (opts->restart < 1 || opts->restart > 512) return fail(HB_ERR_ARG, "restart must be 1..512");
+  if (opts->max_newton < 0 || opts->max_gmres < 1) return fail(HB_ERR_ARG, "bad iteration limits");
+  if (std::isnan(opts->omega_hat)) return fail(HB_ERR_ARG, "omega_hat is NaN");
+  return tm_march_run(const_cast<hb_mesh*>(mesh), prm, bc, Y, A, traj, opts, report,
+                      (hipStream_t)stream, t0);
+}
 
 int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
                     const hb_solve_opts* opts, hb_solve_report* report, void* stream) {

@@ -51,6 +51,7 @@ enum {
 struct Phys {
   double rho, mu, nu, C_I, beta, omega;
   double inv_rho;    // 1 / rho
+  double tau_add;    // added inside tau's bracket: 0 for HB, omega-hat^2 for a marched step
   double shift;      // pseudo-time mass coefficient on velocity rows (0 = none)
   const double* shift_dev;  // if set, the exact-Jv kernel reads the shift here instead
                             // (replayed graphs stay valid when the shift changes)
@@ -147,5 +148,18 @@ template <typename TU>
 hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const uint8_t* dmask,
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st);
 hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st);
+// Time-marching step: S[a][4+i][0] -= cu y_old[i][a] + ca a_old[i][a] (N = 1).
+hipError_t tm_history(const DevMesh& m, double* S, const double* y_old, const double* a_old,
+                      double cu, double ca, hipStream_t st);
+// out [3][n] = modal data d [3][2K+1][n] evaluated at time t.
+hipError_t modal_eval(const DevMesh& m, int K, double omega, double t, const double* d,
+                      double* out, hipStream_t st);
+// out[0] = sum_a mass_a |u_a|^2 (velocity rows of y [4][n]), out[1] = the same
+// of a [3][n]; part holds 2 nb doubles (nb workgroups, nb >= 1).
+hipError_t tm_norms(const DevMesh& m, const double* y, const double* a, double* part, int nb,
+                    double* out, hipStream_t st);
+// a [3][n] = (velocity rows of y_new - y_old) * inv_dt.
+hipError_t tm_accel(const DevMesh& m, const double* y_new, const double* y_old, double* a,
+                    double inv_dt, hipStream_t st);
 
 }  // namespace hb

@@ -708,7 +708,8 @@ __device__ __forceinline__ int64_t residual_lane(const DevMesh& m, const Phys& p
   for (int i = 0; i < 3; ++i) adv[i] = uq[0] * Gm[i][0] + uq[1] * Gm[i][1] + uq[2] * Gm[i][2];
   xi_mul(G, uq, xu);
   const double tau =
-      rsqrt_nr(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + p.C_I * p.nu * p.nu * G.xixi);
+      rsqrt_nr(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + p.C_I * p.nu * p.nu * G.xixi +
+               p.tau_add);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     gal[i] = rho * (hq[i] + adv[i]);
@@ -787,7 +788,8 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
   }
   xi_mul(G, uq, xu);
   const R tau =
-      rsqrt_nr(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + R(p.C_I * p.nu * p.nu) * G.xixi);
+      rsqrt_nr(uq[0] * xu[0] + uq[1] * xu[1] + uq[2] * xu[2] + R(p.C_I * p.nu * p.nu) * G.xixi +
+               R(p.tau_add));
   const R dtau = -tau * tau * tau * (xu[0] * duq[0] + xu[1] * duq[1] + xu[2] * duq[2]);
   R sv[3], ds[3], dgal[3];
 #pragma unroll
@@ -923,7 +925,7 @@ k_elem_jvp_paper(DevMesh m, Phys p, const double* __restrict__ Sy, const double*
   const double ddiv = dG[0][0] + dG[1][1] + dG[2][2];
   const double dpbar = 0.25 * (dp[0] + dp[1] + dp[2] + dp[3]);
   const double rho = p.rho;
-  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
+  const double kap0 = p.C_I * p.nu * p.nu * G.xixi + p.tau_add;
   const double w = 0.25 * G.V;
   double rm[4][3], rc[4], z[4][3], dS[3] = {0, 0, 0};
 #pragma unroll
@@ -1002,7 +1004,7 @@ k_elem_jacobi(DevMesh m, Phys p, const double* __restrict__ Sy, double* __restri
 #pragma unroll
   for (int i = 0; i < 3; ++i) us[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
   const double rho = p.rho;
-  const double kap0 = p.C_I * p.nu * p.nu * G.xixi;
+  const double kap0 = p.C_I * p.nu * p.nu * G.xixi + p.tau_add;
   const double w = 0.25 * G.V;
   double kd[4] = {0, 0, 0, 0}, ld[4] = {0, 0, 0, 0}, td[4] = {0, 0, 0, 0}, xd[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -1677,5 +1679,146 @@ HB_INST_IO(float, double)
 HB_INST_T(double)
 HB_INST_T(float)
 #undef HB_INST_T
+
+// ------------------------------------------------------------ time marching
+// One generalized-alpha step at one time level: the state samples' H u
+// channels hold (c1/dt) u_{n+1} (the time table's derivative entry); the
+// step's history c1/dt u_n + (c1 - 1) a_n is subtracted so that they hold
+// the acceleration at alpha_m.  S is node-major [a][7][1]; y_old [4][n]
+// (velocity rows read) and a_old [3][n] are component-major.
+__global__ void __launch_bounds__(256)
+k_tm_history(int64_t n, double* __restrict__ S, const double* __restrict__ y_old,
+             const double* __restrict__ a_old, double cu, double ca) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    S[a * NCH + 4 + i] -= cu * y_old[i * n + a] + ca * a_old[i * n + a];
+}
+
+hipError_t tm_history(const DevMesh& m, double* S, const double* y_old, const double* a_old,
+                      double cu, double ca, hipStream_t st) {
+  if (m.n == 0) return hipSuccess;
+  const int64_t nb = (m.n + 255) / 256;
+  hipLaunchKernelGGL(k_tm_history, dim3((unsigned)nb), dim3(256), 0, st, m.n, S, y_old, a_old,
+                     cu, ca);
+  return hipGetLastError();
+}
+
+// q(t) = a0 + sum_m a_m cos(m w t) + b_m sin(m w t) of the modal data
+// d [3][2K+1][n] at one time t: out [3][n].
+__global__ void __launch_bounds__(256)
+k_modal_eval(int64_t n, int K, double omega, double t, const double* __restrict__ d,
+             double* __restrict__ out) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const int N = 2 * K + 1;
+  double v[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = d[((int64_t)i * N) * n + a];
+  for (int j = 1; j <= K; ++j) {
+    double sn, cs;
+    sincos((double)j * omega * t, &sn, &cs);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      v[i] += cs * d[((int64_t)i * N + 2 * j - 1) * n + a] + sn * d[((int64_t)i * N + 2 * j) * n + a];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[(int64_t)i * n + a] = v[i];
+}
+
+// Mass-weighted squares of the velocity rows of y [4][n] and of a [3][n]:
+// part[b] and part[nb + b] per workgroup b (grid-stride over nodes).
+__global__ void __launch_bounds__(256)
+k_tm_norms(int64_t n, const double* __restrict__ w, const double* __restrict__ y,
+           const double* __restrict__ a, double* __restrict__ part) {
+  __shared__ double su[256], sa[256];
+  double u2 = 0.0, a2 = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double pu = 0.0, pa = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double yu = y[(int64_t)i * n + k], ya = a[(int64_t)i * n + k];
+      pu += yu * yu;
+      pa += ya * ya;
+    }
+    u2 += w[k] * pu;
+    a2 += w[k] * pa;
+  }
+  su[threadIdx.x] = u2;
+  sa[threadIdx.x] = a2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      su[threadIdx.x] += su[threadIdx.x + s];
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = su[0];
+    part[gridDim.x + blockIdx.x] = sa[0];
+  }
+}
+
+// out[0..1] = sums of the two rows of part [2][nb] (one workgroup).
+__global__ void __launch_bounds__(256)
+k_tm_norms_sum(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double su[256], sa[256];
+  double u2 = 0.0, a2 = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    u2 += part[b];
+    a2 += part[nb + b];
+  }
+  su[threadIdx.x] = u2;
+  sa[threadIdx.x] = a2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      su[threadIdx.x] += su[threadIdx.x + s];
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = su[0];
+    out[1] = sa[0];
+  }
+}
+
+// a_{n+1} = (u_{n+1} - u_n) / (gamma dt) with gamma = 1 (rho_inf = 0).
+__global__ void __launch_bounds__(256)
+k_tm_accel(int64_t n, const double* __restrict__ y_new, const double* __restrict__ y_old,
+           double* __restrict__ a, double inv_dt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    a[(int64_t)i * n + k] = (y_new[(int64_t)i * n + k] - y_old[(int64_t)i * n + k]) * inv_dt;
+}
+
+hipError_t modal_eval(const DevMesh& m, int K, double omega, double t, const double* d,
+                      double* out, hipStream_t st) {
+  if (m.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_modal_eval, dim3((unsigned)((m.n + 255) / 256)), dim3(256), 0, st, m.n,
+                     K, omega, t, d, out);
+  return hipGetLastError();
+}
+
+hipError_t tm_norms(const DevMesh& m, const double* y, const double* a, double* part, int nb,
+                    double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_tm_norms, dim3((unsigned)nb), dim3(256), 0, st, m.n, m.mass, y, a, part);
+  hipLaunchKernelGGL(k_tm_norms_sum, dim3(1), dim3(256), 0, st, nb, (const double*)part, out);
+  return hipGetLastError();
+}
+
+hipError_t tm_accel(const DevMesh& m, const double* y_new, const double* y_old, double* a,
+                    double inv_dt, hipStream_t st) {
+  if (m.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tm_accel, dim3((unsigned)((m.n + 255) / 256)), dim3(256), 0, st, m.n,
+                     y_new, y_old, a, inv_dt);
+  return hipGetLastError();
+}
 
 }  // namespace hb
