@@ -22,6 +22,9 @@ The line reports:
   jv_public    throughput of the public modal hb_jvp entry point;
   tm_step_jv   one time-marching step's exact Jv (hb_tm_jvp) on the same
                mesh, and how many of them one HB Jv costs;
+  tm_vs_hb     the paper's comparison on the Womersley pipe: the GLS
+               time-marching solver marched period by period against the
+               HB solve (wall time, cycle-to-cycle change, difference);
   time_to_1e8  a complete FP64 solve to 1e-8 of the Womersley-pipe workload
                (1,911 nodes, K = 2) from its plain start;
   roofline     the element Jacobian-vector kernel against the FP64 vector
@@ -176,6 +179,70 @@ def womersley_time_to_solution(hbl, torch, log, precision="fp64"):
                "r_final_rel": r["r_final"] / r["r0"]}
     log(f"womersley pipe time to 1e-8: {res}")
     return res
+
+
+def tm_vs_hb(hbl, torch, log, periods, spp):
+    """The paper's comparison on the Womersley-pipe workload: the GLS
+    time-marching solver (hb_tm_march, dt = T/spp, per-step Newton to three
+    orders and GMRES to 0.03, the paper's settings for both solvers) marched
+    period by period from the plain start, against the HB solve to 1e-8.
+    Per period: wall time, cycle-to-cycle change of the marched states and
+    their difference from the HB solution at the same times."""
+    from dataclasses import replace
+    from hbinputs.problems import c1_womersley
+    P = c1_womersley()
+    prm = P.params
+    n, N, K, T = P.mesh.n_nodes, prm.N, prm.K, prm.period
+    w = 2 * np.pi / T
+    gm = hbl.Mesh.from_mesh(P.mesh)
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")  # noqa: E731
+    bc = hbl.BC(to(P.dirichlet), P.outlet_h, P.outlet_R)
+    bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], None)
+    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
+    hbl.newton_solve(gm, replace(prm, K=0), bc0, Ys,
+                     hbl.SolveOptions(rtol=1e-10, max_newton=60, max_gmres=500))
+    Yhb = torch.zeros((4, N, n), dtype=torch.float64, device="cuda:0")
+    Yhb[:, 0] = Ys[:, 0]
+    torch.cuda.synchronize()
+    t = time.time()
+    rhb = hbl.newton_solve(gm, prm, bc, Yhb, hbl.SolveOptions(rtol=1e-8, max_newton=300,
+                                                               max_gmres=500))
+    t_hb = time.time() - t
+    Yh = Yhb.cpu().numpy()
+    dt = T / spp
+    tt = dt * np.arange(1, spp + 1)
+    basis = np.ones((spp, N))
+    for j in range(1, K + 1):
+        basis[:, 2 * j - 1] = np.cos(j * w * tt)
+        basis[:, 2 * j] = np.sin(j * w * tt)
+    hb_t = np.einsum("sm,fmn->sfn", basis, Yh)               # HB solution at the step times
+    Y = Ys[:, 0].contiguous().clone()
+    A = torch.zeros((3, n), dtype=torch.float64, device="cuda:0")
+    traj = torch.empty((spp, 4, n), dtype=torch.float64, device="cuda:0")
+    prev = None
+    per = []
+    t_total = 0.0
+    for k in range(periods):
+        opts = hbl.TmOptions(t0=k * T, dt=dt, n_steps=spp, rtol=1e-3, gmres_eta=0.03,
+                             max_newton=10, max_gmres=500)
+        torch.cuda.synchronize()
+        t = time.time()
+        r = hbl.tm_march(gm, prm, bc, Y, A, opts, traj=traj, raise_on_noconv=False)
+        t_total += time.time() - t
+        cur = traj.cpu().numpy()
+        row = {"period": k + 1, "wall_s": r["wall_s"], "newton_iters": r["newton_iters"],
+               "gmres_iters": r["gmres_iters"], "status": r["status"],
+               "cycle_change": None if prev is None else
+               float(np.linalg.norm(cur - prev) / np.linalg.norm(cur)),
+               "diff_from_hb": float(np.linalg.norm(cur - hb_t) / np.linalg.norm(hb_t))}
+        per.append(row)
+        prev = cur
+    out = {"workload": "womersley_pipe", "n_nodes": n, "steps_per_period": spp,
+           "hb_seconds": t_hb, "hb_newton_iters": rhb["newton_iters"],
+           "hb_gmres_iters": rhb["gmres_iters"], "tm_seconds": t_total, "tm_periods": per}
+    log(f"time marching vs HB: HB {t_hb:.2f} s; marching {periods} periods {t_total:.2f} s; "
+        f"last period change {per[-1]['cycle_change']}, diff from HB {per[-1]['diff_from_hb']:.3e}")
+    return out
 
 
 def learned_warm_start(torch, log, n_train, n_test, K=2):
@@ -360,6 +427,9 @@ def main():
     ap.add_argument("--learned-test", type=int, default=12)
     ap.add_argument("--cfl-study", choices=["tjunction", "womersley"], default=None,
                     help="fixed-pseudo-step CFL study on this workload (skips the main bench)")
+    ap.add_argument("--tm-periods", type=int, default=6,
+                    help="periods of the time-marching comparison on the Womersley pipe (0: off)")
+    ap.add_argument("--tm-spp", type=int, default=50, help="time-marching steps per period")
     ap.add_argument("--branching", type=int, default=0,
                     help="Newton steps of the branching-artery leg (0: skip it; the mesh "
                          "takes about a minute to generate)")
@@ -521,6 +591,8 @@ def main():
         if not args.no_time_to_solution:
             out["time_to_1e8"] = {p_: womersley_time_to_solution(hbl, torch, log, p_)
                                   for p_ in res}
+        if args.tm_periods > 0:
+            out["tm_vs_hb"] = tm_vs_hb(hbl, torch, log, args.tm_periods, args.tm_spp)
         if args.branching > 0:
             out["branching_artery"] = branching_leg(hbl, torch, log, args.branching)
         if args.learned_train > 0:

@@ -105,3 +105,66 @@ def test_tm_argument_errors(c1):
         with pytest.raises(hbl.HBError) as e:
             hbl.tm_residual(c1.gm, P.params, tm, dev(y))
         assert e.value.status == hbl.HB_ERR_ARG
+
+
+def _small_pipe():
+    """259-node pipe, Q = 1 + 0.5 sin(w t), resistance outlet with a modal
+    traction (exercises h(t) and R Q at every step)."""
+    from hbinputs.meshes import cylinder_mesh
+    from hbinputs.problems import Params, Problem, poiseuille_dirichlet, womersley_like_flow
+    m = cylinder_mesh(1.0, 6.0, 3, 6)
+    K = 2
+    prm = Params(K=K, period=1.0)
+    d = poiseuille_dirichlet(m, K, [womersley_like_flow(K)])
+    oh = np.array([[0.2, 0.05, -0.1, 0.0, 0.03]])
+    return Problem("pipe", m, prm, d, oh, np.array([0.5]), u_ref=2 / np.pi)
+
+
+@pytest.mark.parametrize("what", [None, 2.0])
+def test_tm_march_matches_oracle(what):
+    """hb_tm_march against oracle.march: every step's state, the final
+    acceleration.  Both sides solve each step to ||r|| <= 1e-12 ||r_0||, so
+    the states agree to the step Jacobian's conditioning times that."""
+    P = _small_pipe()
+    om, prm = fem.from_mesh(P.mesh), P.params
+    gm = hbl.Mesh.from_mesh(P.mesh)
+    K, w = prm.K, 2 * np.pi / prm.period
+    dt, n_steps = 0.02, 8
+    print(f"tm march what={what} n={om.n} steps={n_steps}", flush=True)
+    y0 = np.zeros((4, om.n))
+    g0 = march.modal_at(P.dirichlet, K, w, 0.0)
+    y0[:3][:, om.dirichlet] = g0[:, om.dirichlet]
+    a0 = np.zeros((3, om.n))
+    ys, a_ref, rep_ref = march.march(
+        om, prm, y0, a0, dt, n_steps, lambda t: march.modal_at(P.dirichlet, K, w, t),
+        lambda t: march.modal_at(P.outlet_h[:, :, None], K, w, t)[:, 0], P.outlet_R,
+        what=what, rtol=1e-12, atol=0.0, eta=1e-8)
+    assert rep_ref.max_step_residual < 1e-9
+    Y, A = dev(y0), dev(a0)
+    traj = torch.empty((n_steps, 4, om.n), dtype=torch.float64, device="cuda")
+    bc = hbl.BC(dev(P.dirichlet), P.outlet_h, P.outlet_R)
+    opts = hbl.TmOptions(dt=dt, n_steps=n_steps, rtol=1e-12, atol=0.0, gmres_eta=1e-8,
+                         max_newton=30, max_gmres=2000, omega_hat=-1.0 if what is None else what)
+    rep = hbl.tm_march(gm, prm, bc, Y, A, opts, traj=traj)
+    assert rep["steps"] == n_steps and rep["status"] == hbl.HB_OK
+    got = host(traj)
+    for k in range(n_steps):
+        e = rel(got[k], ys[k + 1])
+        assert e <= 1e-9, (k, e)
+    assert rel(host(Y), ys[-1]) <= 1e-9
+    assert rel(host(A), a_ref) <= 1e-7
+
+
+def test_tm_march_zero_steps_and_errors(c1):
+    P = c1.P
+    n = c1.om.n
+    y0 = np.random.default_rng(9).standard_normal((4, n))
+    Y, A = dev(y0), dev(np.zeros((3, n)))
+    bc = hbl.BC(dev(P.dirichlet), P.outlet_h, P.outlet_R)
+    rep = hbl.tm_march(c1.gm, P.params, bc, Y, A, hbl.TmOptions(n_steps=0))
+    assert rep["steps"] == 0 and np.array_equal(host(Y), y0)
+    for bad in (dict(dt=0.0), dict(n_steps=-1), dict(rtol=0.0), dict(restart=0),
+                dict(omega_hat=float("nan"))):
+        with pytest.raises(hbl.HBError) as e:
+            hbl.tm_march(c1.gm, P.params, bc, Y, A, hbl.TmOptions(**bad))
+        assert e.value.status == hbl.HB_ERR_ARG
