@@ -59,7 +59,7 @@ ELEM_FLOPS = {"exact": 1680, "paper": 970, "residual": 1040}
 # size, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) counters,
 # each scale read off a plain 1 GiB device copy; valid while the
 # element-kernel source section hashes to the recorded value.
-ELEM_TRAFFIC = {"sha256_prefix": "00647bcc99c7fb0f", "fetch_kib": 394028, "write_kib": 1193487,
+ELEM_TRAFFIC = {"sha256_prefix": "85dde60c62f4d23e", "fetch_kib": 394036, "write_kib": 1193487,
                 "fetch_scale": 2.0, "write_scale": 1.0, "n_nodes": 158688, "n_tets": 848252,
                 "K": 10, "profile": "profiles/k_elem_jvp_exact_tjunction_K10_traffic.md"}
 

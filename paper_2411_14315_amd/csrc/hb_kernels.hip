@@ -814,7 +814,7 @@ __device__ __forceinline__ int64_t jvp_exact_lane(const DevMesh& m, const Phys& 
   }
   quad_gather_rows(cr, res);
   const R V = G.V;
-  const R ms = R(p.shift_dev ? *p.shift_dev : p.shift) * V * R(1.0 / 20.0);
+  const R ms = R(p.shift) * V * R(1.0 / 20.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     res[i] += V * (R(p.mu) * (gA[0] * dG[i][0] + gA[1] * dG[i][1] + gA[2] * dG[i][2]) - gA[i] * dpbar)
@@ -847,6 +847,10 @@ k_elem_block(DevMesh m, Phys p, const R* __restrict__ Sy, const R* __restrict__ 
   const int U = eb.ptr[b + 1] - p0;
   for (int i = threadIdx.x; i < U * CN; i += BLK) sacc[i] = 0.0;
   __syncthreads();
+  // a replayed graph reads the pseudo-time shift from device memory, once
+  // per workgroup, so that the lane code sees a plain value
+  Phys q = p;
+  if (KIND == 1 && p.shift_dev) q.shift = *p.shift_dev;
   const int total = nel * N * 4;
   for (int it = threadIdx.x; it < total; it += BLK) {  // quads stay aligned (BLK % 4 == 0)
     const int A = it & 3;
@@ -856,9 +860,9 @@ k_elem_block(DevMesh m, Phys p, const R* __restrict__ Sy, const R* __restrict__ 
     const int64_t t = e0 + el;
     R r[NCH];
     if constexpr (KIND == 0)
-      residual_lane(m, p, Sy, t, s, A, r);
+      residual_lane(m, q, Sy, t, s, A, r);
     else
-      jvp_exact_lane<R>(m, p, Sy, Sv, t, s, A, r);
+      jvp_exact_lane<R>(m, q, Sy, Sv, t, s, A, r);
     double* dst = sacc + eb.slot[A * m.ne + t] * CN + s;
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
