@@ -240,18 +240,18 @@ k_modal_to_samples(int64_t n, int N, const TI* __restrict__ Y, const double* __r
 // Samples acc[a][c][s] -> modal R[f][m][a].  Momentum rows receive -H z,
 // i.e. -FwdD applied to the z channels (use_z), and are zeroed at Dirichlet
 // nodes when zero_dir_rows.
-template <typename TA, typename TO>
+template <typename TA, typename TO, int TL>
 __global__ void __launch_bounds__(BLK)
 k_samples_to_modal(int64_t n, int N, const TA* __restrict__ acc, int use_z, int zero_dir_rows,
                    int in_ch, const uint8_t* __restrict__ dmask, const double* __restrict__ tab,
                    TO* __restrict__ R) {
   extern __shared__ double sm[];
   const int CN = in_ch * N;
-  double* sA = sm;              // [TN][in_ch][N]
-  double* sF = sA + TN * CN;    // Fwd [m][s]
+  double* sA = sm;              // [TL][in_ch][N]
+  double* sF = sA + TL * CN;    // Fwd [m][s]
   double* sG = sF + N * N;      // FwdD [m][s]
-  const int64_t a0 = (int64_t)blockIdx.x * TN;
-  const int tn = (int)min<int64_t>(TN, n - a0);
+  const int64_t a0 = (int64_t)blockIdx.x * TL;
+  const int tn = (int)min<int64_t>(TL, n - a0);
   const int NN = N * N;
   for (int i = threadIdx.x; i < NN; i += BLK) {
     sF[i] = tab[TAB_FWD * NN + i];
@@ -261,7 +261,7 @@ k_samples_to_modal(int64_t n, int N, const TA* __restrict__ acc, int use_z, int 
   for (int i = threadIdx.x; i < tn * CN; i += BLK) sA[i] = (double)ap[i];
   __syncthreads();
   if constexpr (std::is_same<TO, float>::value) {
-    if (N <= 32 && TN == 32) {
+    if (N <= 32 && TL == 32) {
       // 4 tiles (one per field): Fwd A_f, minus FwdD z_f on momentum rows
       const int lane = threadIdx.x & 63;
       const int f = threadIdx.x >> 6;  // BLK / 64 == 4 wavefronts, one field each
@@ -1446,9 +1446,13 @@ template <typename TA, typename TO>
 hipError_t samples_to_modal(const DevMesh& m, int N, const TA* acc, int use_z, int zero_dir_rows,
                             int in_ch, const double* tab, TO* R, hipStream_t st) {
   if (m.n == 0) return hipSuccess;
-  const size_t lds = sizeof(double) * (TN * in_ch * N + 2 * N * N);
-  hipLaunchKernelGGL((k_samples_to_modal<TA, TO>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N,
-                     acc, use_z, zero_dir_rows, in_ch, m.dmask, tab, R);
+  // FP64 output: 16-node tiles (half the LDS, twice the workgroups per CU in
+  // flight); FP32 output: 32-node tiles for the 32 x 32 MFMA path
+  constexpr int TL = std::is_same<TO, float>::value ? TN : 16;
+  const size_t lds = sizeof(double) * (TL * in_ch * N + 2 * N * N);
+  hipLaunchKernelGGL((k_samples_to_modal<TA, TO, TL>), dim3((unsigned)((m.n + TL - 1) / TL)),
+                     dim3(BLK), lds, st, m.n, N, acc, use_z, zero_dir_rows, in_ch, m.dmask, tab,
+                     R);
   return hipGetLastError();
 }
 
