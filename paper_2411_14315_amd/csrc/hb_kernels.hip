@@ -161,26 +161,26 @@ __device__ inline int mfma_row(int r) { return 8 * (r >> 2) + 4 * ((threadIdx.x 
 // derivative of the velocity (H u).  Dirichlet velocity entries are replaced
 // by the boundary data (zero_dirichlet = 0) or by zero (= 1).  Optionally
 // clears the element accumulator of the tile and a short vector.
-template <typename TI, typename TO>
+template <typename TI, typename TO, int TL>
 __global__ void __launch_bounds__(BLK)
 k_modal_to_samples(int64_t n, int N, const TI* __restrict__ Y, const double* __restrict__ dir,
                    const uint8_t* __restrict__ dmask, int zero_dirichlet,
                    const double* __restrict__ tab, TO* __restrict__ S,
                    TO* __restrict__ acc, double* __restrict__ qz, int nq) {
   extern __shared__ double sm[];
-  double* sY = sm;              // [4][N][TN]
-  double* sB = sY + 4 * N * TN; // Binv [s][m]
+  double* sY = sm;              // [4][N][TL]
+  double* sB = sY + 4 * N * TL; // Binv [s][m]
   double* sD = sB + N * N;      // Bder [s][m]
-  const int64_t a0 = (int64_t)blockIdx.x * TN;
-  const int tn = (int)min<int64_t>(TN, n - a0);
+  const int64_t a0 = (int64_t)blockIdx.x * TL;
+  const int tn = (int)min<int64_t>(TL, n - a0);
   const int NN = N * N;
   for (int i = threadIdx.x; i < NN; i += BLK) {
     sB[i] = tab[TAB_BINV * NN + i];
     sD[i] = tab[TAB_BDER * NN + i];
   }
-  for (int i = threadIdx.x; i < 4 * N * TN; i += BLK) {
-    const int al = i % TN;
-    const int fm = i / TN;
+  for (int i = threadIdx.x; i < 4 * N * TL; i += BLK) {
+    const int al = i % TL;
+    const int fm = i / TL;
     double v = 0.0;
     if (al < tn) {
       const int64_t a = a0 + al;
@@ -197,7 +197,7 @@ k_modal_to_samples(int64_t n, int N, const TI* __restrict__ Y, const double* __r
     for (int i = threadIdx.x; i < nq; i += BLK) qz[i] = 0.0;
   __syncthreads();
   if constexpr (std::is_same<TO, float>::value) {
-    if (N <= 32 && TN == 32) {
+    if (N <= 32 && TL == 32) {
       // 7 tiles: Binv Y_f (f < 4) and Bder Y_f (f < 3), one per wavefront
       const int lane = threadIdx.x & 63;
       for (int tile = threadIdx.x >> 6; tile < 7; tile += BLK / 64) {
@@ -205,7 +205,7 @@ k_modal_to_samples(int64_t n, int N, const TI* __restrict__ Y, const double* __r
         const double* T = tile < 4 ? sB : sD;
         const f32x16 c = mfma_tile_split(
             N, [&](int i, int k) { return (i < N && k < N) ? T[i * N + k] : 0.0; },
-            [&](int k, int j) { return k < N ? sY[(f * N + k) * TN + j] : 0.0; });
+            [&](int k, int j) { return k < N ? sY[(f * N + k) * TL + j] : 0.0; });
         const int al = lane & 31;
         if (al < tn) {
           TO* out = S + (a0 + al) * NCH * N + tile * N;
@@ -227,9 +227,9 @@ k_modal_to_samples(int64_t n, int N, const TI* __restrict__ Y, const double* __r
       const double b = sB[s * N + m];
       const double d = sD[s * N + m];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) o[f] += b * sY[(f * N + m) * TN + al];
+      for (int f = 0; f < 4; ++f) o[f] += b * sY[(f * N + m) * TL + al];
 #pragma unroll
-      for (int f = 0; f < 3; ++f) o[4 + f] += d * sY[(f * N + m) * TN + al];
+      for (int f = 0; f < 3; ++f) o[4 + f] += d * sY[(f * N + m) * TL + al];
     }
     TO* out = S + (a0 + al) * NCH * N + s;
 #pragma unroll
@@ -1436,9 +1436,13 @@ hipError_t modal_to_samples(const DevMesh& m, int N, const TI* Y, const double* 
                             int zero_dirichlet, const double* tab, TO* S, TO* acc_zero,
                             double* q_zero, int nq, hipStream_t st) {
   if (m.n == 0) return hipSuccess;
-  const size_t lds = sizeof(double) * (4 * N * TN + 2 * N * N);
-  hipLaunchKernelGGL((k_modal_to_samples<TI, TO>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N,
-                     Y, dir, m.dmask, zero_dirichlet, tab, S, acc_zero, q_zero, nq);
+  // FP64 output: 16-node tiles (more workgroups per CU in flight); FP32
+  // output: 32-node tiles for the 32 x 32 MFMA path
+  constexpr int TL = std::is_same<TO, float>::value ? TN : 16;
+  const size_t lds = sizeof(double) * (4 * N * TL + 2 * N * N);
+  hipLaunchKernelGGL((k_modal_to_samples<TI, TO, TL>), dim3((unsigned)((m.n + TL - 1) / TL)),
+                     dim3(BLK), lds, st, m.n, N, Y, dir, m.dmask, zero_dirichlet, tab, S, acc_zero,
+                     q_zero, nq);
   return hipGetLastError();
 }
 
