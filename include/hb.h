@@ -217,9 +217,14 @@ int hb_tm_march(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, doub
  * diag_n(K_AA) + rho int N_A^2 H plus the stabilisation's time terms
  * diag(X) H - H diag(X) - rho H diag(T) H with T = int tau N_A^2 and
  * X = int rho tau (u.grad N_A) N_A, inverted exactly per node; the pressure
- * rows keep 1 / L_AA (requires K <= 31).  Both change iteration counts, not
- * the root. */
-enum { HB_PREC_JACOBI = 0, HB_PREC_NODE_TIME = 1 };
+ * rows keep 1 / L_AA (requires K <= 31).  HB_PREC_MEANFLOW couples space:
+ * the tangent with frozen advection and tau (eq. K_mat's P, the Galerkin
+ * time term C of eq. ctangent and the stabilisation's time terms), with
+ * every coefficient replaced by its mean over the samples, is block-diagonal
+ * in the Fourier modes; each mode's complex system (H -> i m w) is
+ * approximated by V-cycles of an aggregation multigrid on the node graph
+ * (see hb_precond_apply).  All change iteration counts, not the root. */
+enum { HB_PREC_JACOBI = 0, HB_PREC_NODE_TIME = 1, HB_PREC_MEANFLOW = 2 };
 
 /* hb_solve_opts.precision: HB_F64 (= 0), or HB_MIXED: FP32 Krylov basis and
  * FP32 Jacobian-vector products (on an FP32 copy of the state) inside GMRES,
@@ -253,6 +258,23 @@ typedef struct {
                         once as a HIP graph (kept with the mesh) and replay it.
                         Results agree to rounding.  With graphs, report.jv_ms
                         also includes the Gram-Schmidt work of each step.    */
+  int32_t amg_sweeps; /* HB_PREC_MEANFLOW: Jacobi sweeps before and after each
+                         coarse correction (0: 2)                               */
+  int32_t amg_cycles; /* HB_PREC_MEANFLOW: V-cycles per application (0: 1)      */
+  double amg_weight;  /* HB_PREC_MEANFLOW: Jacobi damping (0: 0.7)              */
+  double reject_ratio; /* a step whose residual exceeds reject_ratio times the
+                          previous one (or is not finite) is damped by 1/2,
+                          1/4, ... 1/64 until the residual falls below the
+                          previous one; the trial with the smallest residual
+                          is kept; 0: 3.0; < 0: take every full step          */
+  double dt_growth;   /* after an accepted step the pseudo step is scaled by the
+                         residual ratio, and by at least dt_growth when the
+                         residual did not grow (0: 1, plain switched evolution
+                         relaxation)                                             */
+  int32_t amg_aggregation; /* HB_PREC_MEANFLOW: 0 two passes of pairwise matching,
+                              1 a node with its free neighbours                 */
+  double amg_coarse_weight; /* HB_PREC_MEANFLOW: weight of the coarse-level
+                               correction (0: 0.7)                              */
 } hb_solve_opts;
 
 typedef struct {
@@ -265,12 +287,14 @@ typedef struct {
   double wall_s;
   double jv_ms;    /* total time spent in Krylov operator applications */
   int32_t n_jv;
+  int32_t rejected; /* Newton steps taken damped (alpha < 1)          */
 } hb_solve_report;
 
 /* Inexact Newton with pseudo-time continuation (Section 2.3): the tangent
  * receives c1 rho/dt int N_A N_B on velocity rows, dt grows by switched
- * evolution relaxation; right-Jacobi-preconditioned restarted GMRES with
- * classical Gram-Schmidt run twice.  Y (device [4][N][n]) holds the initial
+ * evolution relaxation (steps that raise the residual beyond reject_ratio
+ * are damped); right-preconditioned restarted
+ * GMRES with classical Gram-Schmidt run twice.  Y (device [4][N][n]) holds the initial
  * guess on entry and the solution on return.  Returns HB_OK on convergence,
  * HB_ERR_NOCONV with Y = last iterate otherwise; the report is filled in both
  * cases.  The Krylov basis ((restart + 1) x 4 N n values) and the other solver
@@ -279,6 +303,38 @@ typedef struct {
  * overlap. */
 int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, double* Y,
                     const hb_solve_opts* opts, hb_solve_report* report, void* stream);
+
+/* The mean-flow modal preconditioner (HB_PREC_MEANFLOW) on its own, for
+ * checking it.  At the state Y (device [4][N][n], Dirichlet entries from bc)
+ * and pseudo-time mass coefficient `shift` (>= 0, the c1 rho / dt of the
+ * solve), the operator A is, for each harmonic m (H -> i m w), the sample
+ * mean of the tangent with frozen advection and tau: eq. K_mat's blocks,
+ * the Galerkin time term of eq. ctangent and the stabilisation's time
+ * terms, without outlet terms; Dirichlet velocity rows and columns removed.
+ * op = 0: OUT = A X.  op = 1: OUT = M^-1 X, M^-1 = `cycles` V-cycles of an
+ * aggregation multigrid with `sweeps` block-Jacobi sweeps (weight `weight`)
+ * before and after each coarse correction (weight `coarse_weight`)
+ * per level and a dense inverse on the coarsest level, which holds at most
+ * `coarse_max` nodes (a mesh with at most coarse_max nodes is solved
+ * exactly).  X and OUT are device [4][N][n] modal arrays; X's Dirichlet
+ * velocity entries are taken as 0 and OUT's are 0.  The hierarchy is built
+ * on first use and kept with the mesh.  Asynchronous on the stream.
+ * HB_ERR_ARG for a bad op, sizes or options; HB_ERR_NOCONV if the
+ * coarsest-level matrix is singular (op = 1 only; waits for the stream). */
+typedef struct {
+  int32_t sweeps;        /* >= 1                                              */
+  int32_t cycles;        /* >= 1                                              */
+  double weight;         /* Jacobi damping, (0, 1]                            */
+  int32_t coarse_max;    /* 1..256                                            */
+  int32_t aggregation;   /* 0 pairwise matching twice, 1 node + neighbours    */
+  double coarse_weight;  /* weight of the coarse-level correction, (0, 2]     */
+} hb_precond_opts;
+int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+                     double shift, const hb_precond_opts* opts, int32_t op, const double* X,
+                     double* OUT, void* stream);
+/* Node counts of the preconditioner's levels (finest first): sizes[0..max-1];
+ * *n_levels = number of levels (0 before the hierarchy is built). */
+int hb_precond_levels(const hb_mesh* mesh, int64_t* sizes, int32_t max, int32_t* n_levels);
 
 /* Per-stage timing of hb_residual / hb_jvp for profiling.  When enabled,
  * those calls record HIP events on their stream between stages:

@@ -147,3 +147,56 @@ def jacobi_diagonal(om: OMesh, prm, y: np.ndarray, shift: float = 0.0) -> np.nda
         np.add.at(out[1], (np.broadcast_to(s, ld.shape), np.broadcast_to(idx[:, None, :], ld.shape)), ld)
     out[0][:, om.dirichlet] = 1.0
     return out
+
+
+def frozen_tangent_apply(om: OMesh, prm, y: np.ndarray, v: np.ndarray, shift: float = 0.0,
+                         H: np.ndarray | None = None) -> np.ndarray:
+    """Tangent of eq. Rmc with advection and tau frozen at the state y, no
+    outlet terms, applied to v (time samples, (4, N, n)).  With the
+    advecting velocity and tau held at y the residual is linear in its
+    argument, so this is the residual of v itself (v's Dirichlet velocity
+    samples set to zero, traction and backflow off), plus shift * int N_A N_B
+    on the velocity rows.  It is the paper's P of eq. K_mat with the
+    Galerkin time term C of eq. ctangent and the stabilisation's time terms.
+    """
+    from .residual import Options, residual_samples
+    N = y.shape[1]
+    H = H_of_prm(prm) if H is None else H
+    vv = np.array(v, dtype=np.float64, copy=True)
+    vv[:3][:, :, om.dirichlet] = 0.0
+    out = residual_samples(om, prm, vv, np.zeros((om.n_outlets, N)), None, H,
+                           Options(frozen_u=np.asarray(y[:3], dtype=np.float64), backflow=False))
+    if shift != 0.0:
+        M = om.vol[:, None, None] * (np.ones((4, 4)) + np.eye(4)) / 20.0
+        mv = np.zeros((3, N, om.n))
+        idx = om.tets
+        for i in range(3):
+            loc = np.einsum("eab,nbe->nae", M, vv[i][:, idx].transpose(0, 2, 1))
+            for A in range(4):
+                np.add.at(mv[i], (slice(None), idx[:, A]), loc[:, A, :])
+        mv[:, :, om.dirichlet] = 0.0
+        out[:3] += shift * mv
+    return out
+
+
+def meanflow_apply(om: OMesh, prm, y: np.ndarray, v: np.ndarray, shift: float = 0.0) -> np.ndarray:
+    """The frozen-coefficient tangent averaged over cyclic time shifts,
+        A v = (1/N) sum_k S^-k J_f(y) S^k v,   (S^k v)_s = v_(s+k mod N),
+    i.e. its circulant projection in time: every coefficient that varies
+    over the samples is replaced by its sample mean, while H (already
+    circulant) is kept.  The result commutes with time shifts and so maps
+    each harmonic to itself.  This defines the operator that the solver's
+    mean-flow preconditioner approximates (it changes iteration counts, not
+    the root)."""
+    N = y.shape[1]
+    H = H_of_prm(prm)
+    acc = np.zeros_like(np.asarray(v, dtype=np.float64))
+    for k in range(N):
+        w = frozen_tangent_apply(om, prm, y, np.roll(v, -k, axis=1), shift, H)
+        acc += np.roll(w, k, axis=1)
+    return acc / N
+
+
+def H_of_prm(prm) -> np.ndarray:
+    from .spectral import hb_matrix
+    return hb_matrix(prm.K, 2.0 * np.pi / prm.period)

@@ -22,7 +22,7 @@ HB_OK, HB_ERR_ARG, HB_ERR_MESH, HB_ERR_DEVICE, HB_ERR_NOCONV, HB_ERR_NAN, HB_ERR
 HB_JV_EXACT, HB_JV_PAPER, HB_F64, HB_F32 = 0, 1, 0, 2
 HB_MIXED = 1
 HB_F32_BASIS = 2
-HB_PREC_JACOBI, HB_PREC_NODE_TIME = 0, 1
+HB_PREC_JACOBI, HB_PREC_NODE_TIME, HB_PREC_MEANFLOW = 0, 1, 2
 
 
 class HBError(RuntimeError):
@@ -63,13 +63,23 @@ class _Opts(C.Structure):
                 ("cfl", C.c_double), ("c1", C.c_double), ("restart", C.c_int32),
                 ("max_newton", C.c_int32), ("max_gmres", C.c_int32), ("precision", C.c_int32),
                 ("jv_kind", C.c_int32), ("verbose", C.c_int32), ("precond", C.c_int32),
-                ("cfl_max", C.c_double), ("graphs", C.c_int32)]
+                ("cfl_max", C.c_double), ("graphs", C.c_int32), ("amg_sweeps", C.c_int32),
+                ("amg_cycles", C.c_int32), ("amg_weight", C.c_double),
+                ("reject_ratio", C.c_double), ("dt_growth", C.c_double),
+                ("amg_aggregation", C.c_int32), ("amg_coarse_weight", C.c_double)]
+
+
+class _PcOpts(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("cycles", C.c_int32), ("weight", C.c_double),
+                ("coarse_max", C.c_int32), ("aggregation", C.c_int32),
+                ("coarse_weight", C.c_double)]
 
 
 class _Report(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("status", C.c_int32),
                 ("r0", C.c_double), ("r_final", C.c_double), ("r_ref", C.c_double),
-                ("wall_s", C.c_double), ("jv_ms", C.c_double), ("n_jv", C.c_int32)]
+                ("wall_s", C.c_double), ("jv_ms", C.c_double), ("n_jv", C.c_int32),
+                ("rejected", C.c_int32)]
 
 
 _lib = None
@@ -108,12 +118,15 @@ def load():
     lib.hb_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, C.POINTER(C.c_double), vp]
     lib.hb_mlp_adam_step.argtypes = [vp, vp, C.c_float, vp]
     lib.hb_pod_expand.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp]
+    lib.hb_precond_apply.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, dbl,
+                                     C.POINTER(_PcOpts), i32, vp, vp, vp]
+    lib.hb_precond_levels.argtypes = [vp, vp, i32, C.POINTER(i32)]
     lib.hb_last_error.restype = C.c_char_p
     for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
                  "hb_newton_solve", "hb_set_timing", "hb_last_timings", "hb_mlp_create",
                  "hb_mlp_num_params", "hb_mlp_get_params", "hb_mlp_forward", "hb_mlp_loss_grad",
                  "hb_mlp_adam_step", "hb_pod_expand", "hb_tm_residual", "hb_tm_jvp",
-                 "hb_tm_march"):
+                 "hb_tm_march", "hb_precond_apply", "hb_precond_levels"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -129,6 +142,34 @@ def _ptr(t) -> int:
     if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
         raise HBError(HB_ERR_ARG, "expected a contiguous device tensor")
     return t.data_ptr()
+
+
+def _arg(t, name, shape, dtypes=("float64",), device=None):
+    """Check a device tensor argument before anything is launched: contiguous,
+    on the device, of one of ``dtypes`` and exactly ``shape``; same device as
+    ``device`` if given.  Returns its pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise HBError(HB_ERR_ARG, f"{name}: expected a device tensor")
+    if str(t.dtype).replace("torch.", "") not in dtypes:
+        raise HBError(HB_ERR_ARG, f"{name}: dtype {t.dtype}, expected {'/'.join(dtypes)}")
+    if tuple(t.shape) != tuple(shape):
+        raise HBError(HB_ERR_ARG, f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise HBError(HB_ERR_ARG, f"{name}: expected a contiguous device tensor")
+    if device is not None and t.device != device:
+        raise HBError(HB_ERR_ARG, f"{name}: on {t.device}, expected {device}")
+    return t.data_ptr()
+
+
+def _host(a, name, shape):
+    """Check a host array argument (None allowed) and return its pointer."""
+    if a is None:
+        return None
+    if a.dtype != np.float64 or a.shape != tuple(shape) or not a.flags.c_contiguous:
+        raise HBError(HB_ERR_ARG, f"{name}: expected float64 {tuple(shape)}, got "
+                                  f"{a.dtype} {a.shape}")
+    return a.ctypes.data
 
 
 def _stream(stream):
@@ -216,10 +257,15 @@ class BC:
         self.outlet_h = None if outlet_h is None else np.ascontiguousarray(outlet_h, np.float64)
         self.outlet_R = None if outlet_R is None else np.ascontiguousarray(outlet_R, np.float64)
 
-    def _c(self):
-        return _BC(_ptr(self.dirichlet),
-                   None if self.outlet_h is None else self.outlet_h.ctypes.data,
-                   None if self.outlet_R is None else self.outlet_R.ctypes.data)
+    def _c(self, mesh=None, N=None):
+        if mesh is None:
+            return _BC(_ptr(self.dirichlet),
+                       None if self.outlet_h is None else self.outlet_h.ctypes.data,
+                       None if self.outlet_R is None else self.outlet_R.ctypes.data)
+        no = mesh.n_outlets
+        hp = _host(self.outlet_h, "bc.outlet_h", (no, N))
+        rp = _host(self.outlet_R, "bc.outlet_R", (no,))
+        return _BC(_arg(self.dirichlet, "bc.dirichlet", (3, N, mesh.n_nodes)), hp, rp)
 
 
 def _params(p):
@@ -228,26 +274,39 @@ def _params(p):
     return Params(p.rho, p.mu, p.period, p.K, p.C_I, p.beta_bf)
 
 
+def _modal_shape(mesh, p):
+    return (4, p.N, mesh.n_nodes)
+
+
 def residual(mesh: Mesh, params, bc: BC, Y, R=None, stream=None):
     import torch
+    p = _params(params)
+    shp = _modal_shape(mesh, p)
+    yp = _arg(Y, "Y", shp)
     if R is None:
         R = torch.empty_like(Y)
-    pc, bcc = _params(params)._c(), bc._c()
-    _check(load().hb_residual(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), _ptr(R),
-                              _stream(stream)))
+    rp = _arg(R, "R", shp, device=Y.device)
+    pc, bcc = p._c(), bc._c(mesh, p.N)
+    _check(load().hb_residual(mesh._h, C.byref(pc), C.byref(bcc), yp, rp, _stream(stream)))
     return R
 
 
 def jvp(mesh: Mesh, params, bc: BC, Y, V, JV=None, kind: str = "exact", stream=None):
     import torch
+    p = _params(params)
+    shp = _modal_shape(mesh, p)
+    yp = _arg(Y, "Y", shp)
+    vp_ = _arg(V, "V", shp, ("float64", "float32"), device=Y.device)
     if JV is None:
         JV = torch.empty_like(V)
+    jp = _arg(JV, "JV", shp, (str(V.dtype).replace("torch.", ""),), device=Y.device)
+    if kind not in ("exact", "paper"):
+        raise HBError(HB_ERR_ARG, f"unknown tangent kind {kind!r}")
     flags = HB_JV_EXACT if kind == "exact" else HB_JV_PAPER
     if V.dtype == torch.float32:
         flags |= HB_F32
-    pc, bcc = _params(params)._c(), bc._c()
-    _check(load().hb_jvp(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), _ptr(V), _ptr(JV), flags,
-                         _stream(stream)))
+    pc, bcc = p._c(), bc._c(mesh, p.N)
+    _check(load().hb_jvp(mesh._h, C.byref(pc), C.byref(bcc), yp, vp_, jp, flags, _stream(stream)))
     return JV
 
 
@@ -263,30 +322,37 @@ class TmStep:
         self.outlet_h = None if outlet_h is None else np.ascontiguousarray(outlet_h, np.float64)
         self.outlet_R = None if outlet_R is None else np.ascontiguousarray(outlet_R, np.float64)
 
-    def _c(self):
-        return _TmStep(self.dt, self.omega_hat, _ptr(self.y_old), _ptr(self.a_old),
-                       _ptr(self.dirichlet),
-                       None if self.outlet_h is None else self.outlet_h.ctypes.data,
-                       None if self.outlet_R is None else self.outlet_R.ctypes.data)
+    def _c(self, mesh):
+        n, no = mesh.n_nodes, mesh.n_outlets
+        return _TmStep(self.dt, self.omega_hat, _arg(self.y_old, "tm.y_old", (4, n)),
+                       _arg(self.a_old, "tm.a_old", (3, n)),
+                       _arg(self.dirichlet, "tm.dirichlet", (3, n)),
+                       _host(self.outlet_h, "tm.outlet_h", (no,)),
+                       _host(self.outlet_R, "tm.outlet_R", (no,)))
 
 
 def tm_residual(mesh: Mesh, params, tm: TmStep, Y, R=None, stream=None):
     import torch
+    n = mesh.n_nodes
+    yp = _arg(Y, "Y", (4, n))
     if R is None:
         R = torch.empty_like(Y)
-    pc, tc = _params(params)._c(), tm._c()
-    _check(load().hb_tm_residual(mesh._h, C.byref(pc), C.byref(tc), _ptr(Y), _ptr(R),
-                                 _stream(stream)))
+    rp = _arg(R, "R", (4, n), device=Y.device)
+    pc, tc = _params(params)._c(), tm._c(mesh)
+    _check(load().hb_tm_residual(mesh._h, C.byref(pc), C.byref(tc), yp, rp, _stream(stream)))
     return R
 
 
 def tm_jvp(mesh: Mesh, params, tm: TmStep, Y, V, JV=None, stream=None):
     import torch
+    n = mesh.n_nodes
+    yp = _arg(Y, "Y", (4, n))
+    vp_ = _arg(V, "V", (4, n), device=Y.device)
     if JV is None:
         JV = torch.empty_like(V)
-    pc, tc = _params(params)._c(), tm._c()
-    _check(load().hb_tm_jvp(mesh._h, C.byref(pc), C.byref(tc), _ptr(Y), _ptr(V), _ptr(JV),
-                            _stream(stream)))
+    jp = _arg(JV, "JV", (4, n), device=Y.device)
+    pc, tc = _params(params)._c(), tm._c(mesh)
+    _check(load().hb_tm_jvp(mesh._h, C.byref(pc), C.byref(tc), yp, vp_, jp, _stream(stream)))
     return JV
 
 
@@ -316,10 +382,14 @@ def tm_march(mesh: Mesh, params, bc: BC, Y, A, opts: TmOptions, traj=None, strea
     at opts.t0 on entry and after the last step on return; ``traj`` (a
     device tensor (n_steps, 4, n)) or None receives every step's state."""
     rep = _TmReport()
-    pc, bcc, oc = _params(params)._c(), bc._c(), opts._c()
-    st = load().hb_tm_march(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), _ptr(A),
-                            None if traj is None else _ptr(traj), C.byref(oc), C.byref(rep),
-                            _stream(stream))
+    p = _params(params)
+    n = mesh.n_nodes
+    yp = _arg(Y, "Y", (4, n))
+    ap_ = _arg(A, "A", (3, n), device=Y.device)
+    tp = None if traj is None else _arg(traj, "traj", (opts.n_steps, 4, n), device=Y.device)
+    pc, bcc, oc = p._c(), bc._c(mesh, p.N), opts._c()
+    st = load().hb_tm_march(mesh._h, C.byref(pc), C.byref(bcc), yp, ap_, tp, C.byref(oc),
+                            C.byref(rep), _stream(stream))
     out = {k: getattr(rep, k) for k, _ in _TmReport._fields_}
     if st != HB_OK and not (st == HB_ERR_NOCONV and not raise_on_noconv):
         _check(st)
@@ -329,10 +399,12 @@ def tm_march(mesh: Mesh, params, bc: BC, Y, A, opts: TmOptions, traj=None, strea
 def jacobi(mesh: Mesh, params, bc: BC, Y, shift: float = 0.0, D=None, stream=None):
     import torch
     p = _params(params)
+    yp = _arg(Y, "Y", _modal_shape(mesh, p))
     if D is None:
         D = torch.empty((2, p.N, mesh.n_nodes), dtype=torch.float64, device=Y.device)
-    pc, bcc = p._c(), bc._c()
-    _check(load().hb_jacobi(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), float(shift), _ptr(D),
+    dp = _arg(D, "D", (2, p.N, mesh.n_nodes), device=Y.device)
+    pc, bcc = p._c(), bc._c(mesh, p.N)
+    _check(load().hb_jacobi(mesh._h, C.byref(pc), C.byref(bcc), yp, float(shift), dp,
                             _stream(stream)))
     return D
 
@@ -353,11 +425,20 @@ class SolveOptions:
     precond: int = HB_PREC_NODE_TIME
     cfl_max: float = 0.0
     graphs: int = 0  # 1: replay captured Arnoldi steps (HIP graphs) at launch-bound sizes
+    amg_sweeps: int = 0   # HB_PREC_MEANFLOW: Jacobi sweeps per level (0: 2)
+    amg_cycles: int = 0   # HB_PREC_MEANFLOW: V-cycles per application (0: 1)
+    amg_weight: float = 0.0  # HB_PREC_MEANFLOW: Jacobi damping (0: 0.7)
+    reject_ratio: float = 0.0  # undo steps whose residual grows beyond this ratio (0: 2; <0: never)
+    dt_growth: float = 0.0     # least pseudo-step growth after a non-increasing step (0: 1)
+    amg_aggregation: int = 0   # HB_PREC_MEANFLOW: 0 pairwise matching twice, 1 node + neighbours
+    amg_coarse_weight: float = 0.0  # HB_PREC_MEANFLOW: coarse-correction weight (0: 0.7)
 
     def _c(self):
         return _Opts(self.rtol, self.r_ref, self.gmres_eta, self.cfl, self.c1, self.restart,
                      self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose,
-                     self.precond, self.cfl_max, self.graphs)
+                     self.precond, self.cfl_max, self.graphs, self.amg_sweeps, self.amg_cycles,
+                     self.amg_weight, self.reject_ratio, self.dt_growth, self.amg_aggregation,
+                     self.amg_coarse_weight)
 
 
 def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None,
@@ -365,10 +446,45 @@ def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None
     """Solve in place (Y holds the guess on entry, the solution on return)."""
     opts = opts or SolveOptions()
     rep = _Report()
-    pc, bcc, oc = _params(params)._c(), bc._c(), opts._c()
-    st = load().hb_newton_solve(mesh._h, C.byref(pc), C.byref(bcc), _ptr(Y), C.byref(oc),
+    p = _params(params)
+    yp = _arg(Y, "Y", _modal_shape(mesh, p))
+    pc, bcc, oc = p._c(), bc._c(mesh, p.N), opts._c()
+    st = load().hb_newton_solve(mesh._h, C.byref(pc), C.byref(bcc), yp, C.byref(oc),
                                 C.byref(rep), _stream(stream))
     out = {k: getattr(rep, k) for k, _ in _Report._fields_}
     if st != HB_OK and not (st == HB_ERR_NOCONV and not raise_on_noconv):
         _check(st)
     return out
+
+
+def precond_apply(mesh: Mesh, params, bc: BC, Y, X, shift: float = 0.0, op: str = "inverse",
+                  sweeps: int = 2, cycles: int = 1, weight: float = 0.7, coarse_max: int = 64,
+                  aggregation: int = 0, coarse_weight: float = 0.7, OUT=None, stream=None):
+    """The mean-flow modal preconditioner at the state Y: ``op="operator"``
+    applies its operator A, ``op="inverse"`` its multigrid approximation of
+    A^-1 (modal (4, N, n) arrays; see hb_precond_apply)."""
+    import torch
+    p = _params(params)
+    shp = _modal_shape(mesh, p)
+    yp = _arg(Y, "Y", shp)
+    xp = _arg(X, "X", shp, device=Y.device)
+    if OUT is None:
+        OUT = torch.empty_like(X)
+    op_ = {"operator": 0, "inverse": 1}.get(op)
+    if op_ is None:
+        raise HBError(HB_ERR_ARG, f"unknown op {op!r}")
+    outp = _arg(OUT, "OUT", shp, device=Y.device)
+    o = _PcOpts(int(sweeps), int(cycles), float(weight), int(coarse_max), int(aggregation),
+                float(coarse_weight))
+    pc, bcc = p._c(), bc._c(mesh, p.N)
+    _check(load().hb_precond_apply(mesh._h, C.byref(pc), C.byref(bcc), yp, float(shift),
+                                   C.byref(o), op_, xp, outp, _stream(stream)))
+    return OUT
+
+
+def precond_levels(mesh: Mesh) -> list:
+    """Node counts of the preconditioner hierarchy's levels (empty before use)."""
+    sizes = np.zeros(32, np.int64)
+    nl = C.c_int32()
+    _check(load().hb_precond_levels(mesh._h, sizes.ctypes.data, 32, C.byref(nl)))
+    return [int(x) for x in sizes[:nl.value]]

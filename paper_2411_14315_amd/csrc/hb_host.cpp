@@ -79,7 +79,7 @@ struct Workspace {
 // Krylov buffers kept on the mesh between solves, pinned host slots for the
 // Arnoldi coefficients, and events.
 struct SolverBufs {
-  DevBuf basis, xvec, rvec, tmp, partial, hdev, rbuf, uc, shift;
+  DevBuf basis, xvec, rvec, tmp, partial, hdev, rbuf, uc, shift, sysave, syfull;
   double* hpin = nullptr;  // pinned host copies of each Arnoldi step's coefficients
   size_t hpin_n = 0;
   hipEvent_t evh[2] = {};  // Arnoldi step completion (ping-pong)
@@ -123,6 +123,9 @@ struct hb_mesh {
   Workspace ws;
   SolverBufs sb;
   DevBuf tm_yold, tm_g, tm_part;  // time marching: previous state, boundary data, norms
+  hb::Precond* pc = nullptr;       // mean-flow preconditioner hierarchy (built on first use)
+  int pc_coarse_max = 0, pc_pairwise = -1;
+  DevBuf pcz;                      // preconditioned vector [n][4][N]
   // stage timing (hb_set_timing)
   bool timing = false;
   bool timed_call = false;
@@ -130,16 +133,18 @@ struct hb_mesh {
   ~hb_mesh() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    hb::precond_destroy(pc);
   }
   size_t bytes_held() const {
     size_t b = 0;
     for (const DevBuf* d : {&tets, &geo, &dmask, &of, &ofn, &oid, &mass, &inlet_dev, &ws.Sy, &ws.Sv,
                             &ws.acc, &ws.tab, &ws.small, &ws.dg, &ws.dinv, &ws.binv, &ws.Sy32,
                             &ws.Sv32, &ws.acc32, &sb.basis, &sb.xvec, &sb.rvec, &sb.tmp,
-                            &sb.partial, &sb.hdev, &sb.rbuf, &sb.uc, &sb.shift, &tm_yold, &tm_g,
+                            &sb.partial, &sb.hdev, &sb.rbuf, &sb.uc, &sb.shift, &sb.sysave, &sb.syfull, &tm_yold, &tm_g,
                             &tm_part})
       b += d->bytes;
     for (const auto& bm : bmaps) b += bm.ptr.bytes + bm.nodes.bytes + bm.slot.bytes;
+    b += pcz.bytes + hb::precond_bytes(pc);
     return b;
   }
 };
@@ -352,6 +357,22 @@ int build_blocks(BlockMap& bm, const std::vector<int32_t>& T, int64_t ne, int si
   bm.eb.slot = bm.slot.as<uint8_t>();
   return HB_OK;
 }
+
+// The mean-flow preconditioner's hierarchy for this mesh (built once per
+// coarse-level size) and its output buffer for N samples.
+int ensure_precond(hb_mesh* m, int coarse_max, int pairwise, int N) {
+  if (!m->pc || m->pc_coarse_max != coarse_max || m->pc_pairwise != pairwise) {
+    hb::precond_destroy(m->pc);
+    m->pc = nullptr;
+    HB_CHECK(hb::precond_create(m->dm.n, m->dm.ne, m->dm.tets, coarse_max, pairwise, &m->pc));
+    m->pc_coarse_max = coarse_max;
+    m->pc_pairwise = pairwise;
+  }
+  HB_CHECK(m->pcz.ensure(sizeof(double) * (size_t)m->dm.n * 4 * N));
+  return HB_OK;
+}
+
+constexpr int kCoarseMax = 64;
 
 }  // namespace
 
@@ -823,6 +844,54 @@ int hb_jacobi(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const 
   return HB_OK;
 }
 
+int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+                     double shift, const hb_precond_opts* o, int32_t op, const double* X,
+                     double* OUT, void* stream) {
+  if (!mesh || !Y || !X || !OUT || !o) return fail(HB_ERR_ARG, "NULL argument");
+  if (op != 0 && op != 1) return fail(HB_ERR_ARG, "op must be 0 or 1");
+  if (!std::isfinite(shift) || shift < 0) return fail(HB_ERR_ARG, "shift must be finite, >= 0");
+  if (o->sweeps < 1 || o->cycles < 1 || !(o->weight > 0 && o->weight <= 1) || o->coarse_max < 1 ||
+      o->coarse_max > 256 || (o->aggregation != 0 && o->aggregation != 1) ||
+      !(o->coarse_weight > 0 && o->coarse_weight <= 2))
+    return fail(HB_ERR_ARG, "bad preconditioner options");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = prepare(m, prm, bc, st);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  const int N = w.N;
+  rc = ensure_precond(m, o->coarse_max, o->aggregation == 0, N);
+  if (rc) return rc;
+  const double* tab = w.tab.as<double>();
+  const Phys p = make_phys(prm, shift);
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab,
+                                                w.Sy.as<double>(), nullptr, nullptr, 0, st));
+  HB_CHECK(hb::precond_setup(m->pc, m->dm, p, w.Sy.as<double>(), shift, o->sweeps, o->cycles,
+                             o->weight, o->coarse_weight, st));
+  // X (Dirichlet velocity entries dropped) to samples [n][7][N]
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, X, bc->dirichlet, 1, tab,
+                                                w.Sv.as<double>(), nullptr, nullptr, 0, st));
+  if (op == 0) {
+    HB_CHECK((hb::precond_matvec<double, double>(m->pc, m->dm.n, w.Sv.as<double>(), hb::NCH,
+                                                 m->pcz.as<double>(), st)));
+  } else {
+    int sing = 0;
+    HB_CHECK(hb::precond_singular(m->pc, &sing, st));
+    if (sing) return fail(HB_ERR_NOCONV, "singular coarsest-level matrix");
+    HB_CHECK((hb::precond_apply<double, double>(m->pc, m->dm.n, w.Sv.as<double>(), hb::NCH,
+                                                m->pcz.as<double>(), st)));
+  }
+  HB_CHECK(hb::samples_to_modal<double, double>(m->dm, N, m->pcz.as<double>(), 0, 1, 4, tab, OUT,
+                                                st));
+  return HB_OK;
+}
+
+int hb_precond_levels(const hb_mesh* mesh, int64_t* sizes, int32_t max, int32_t* n_levels) {
+  if (!mesh || !n_levels || (max > 0 && !sizes)) return fail(HB_ERR_ARG, "NULL argument");
+  *n_levels = hb::precond_levels(mesh->pc, sizes, max);
+  return HB_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------ the solver
@@ -849,6 +918,7 @@ struct Solver {
   int nblk;
   int jv_kind;
   const double* binv = nullptr;  // per-node time blocks, or NULL for the diagonal
+  bool use_pc = false;           // mean-flow modal preconditioner (m->pc)
   bool jv64 = false;  // FP32 basis with FP64 Jacobian-vector products (HB_F32_BASIS)
   bool use_graphs = false;     // replay captured Arnoldi steps
   bool timed_apply = true;     // false while capturing
@@ -969,8 +1039,15 @@ struct Solver {
       int rc = timer_start(pr);
       if (rc) return rc;
     }
-    HB_CHECK(hb::prepare_direction<T, T>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab, Sv,
-                                         acc, s.dQ, m->dm.n_out * N, st));
+    if (use_pc) {
+      HB_CHECK((hb::precond_apply<T, double>(m->pc, m->dm.n, q, 4, m->pcz.as<double>(), st)));
+      HB_CHECK((hb::prepare_direction<double, T>(m->dm, N, m->pcz.as<double>(), 4, nullptr,
+                                                 nullptr, 1, tab, Sv, acc, s.dQ,
+                                                 m->dm.n_out * N, st)));
+    } else {
+      HB_CHECK(hb::prepare_direction<T, T>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab,
+                                           Sv, acc, s.dQ, m->dm.n_out * N, st));
+    }
     if (jv_kind == HB_JV_EXACT) {
       if (s.R) HB_CHECK(hb::outlet_flux<T>(m->dm, N, Sv, s.dQ, st));
       HB_CHECK(hb::elem_jvp_exact<T>(m->dm, p, state(), Sv, acc, pick_blocks(m, N),
@@ -1016,8 +1093,15 @@ struct Solver {
       int rc = timer_start(pr);
       if (rc) return rc;
     }
-    HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab,
-                                                Sv, acc, s.dQ, m->dm.n_out * N, st)));
+    if (use_pc) {
+      HB_CHECK((hb::precond_apply<T, double>(m->pc, m->dm.n, q, 4, m->pcz.as<double>(), st)));
+      HB_CHECK((hb::prepare_direction<double, double>(m->dm, N, m->pcz.as<double>(), 4, nullptr,
+                                                      nullptr, 1, tab, Sv, acc, s.dQ,
+                                                      m->dm.n_out * N, st)));
+    } else {
+      HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1,
+                                                  tab, Sv, acc, s.dQ, m->dm.n_out * N, st)));
+    }
     if (s.R) HB_CHECK(hb::outlet_flux<double>(m->dm, N, Sv, s.dQ, st));
     HB_CHECK(hb::elem_jvp_exact<double>(m->dm, p, w.Sy.as<double>(), Sv, acc,
                                         pick_blocks(m, N), st));
@@ -1042,7 +1126,8 @@ struct Solver {
             (uintptr_t)sb->shift.p, (uintptr_t)binv, (uintptr_t)w.dinv.p, (uintptr_t)w.tab.p,
             (uintptr_t)w.small.p, (uintptr_t)s.R, (uintptr_t)w.Sy.p, (uintptr_t)w.Sv.p,
             (uintptr_t)w.acc.p, (uintptr_t)w.Sy32.p, (uintptr_t)w.Sv32.p, (uintptr_t)w.acc32.p,
-            (uintptr_t)pick_blocks(m, N).ptr, bits(prm->rho), bits(prm->mu), bits(prm->period),
+            (uintptr_t)pick_blocks(m, N).ptr, (uintptr_t)use_pc, (uintptr_t)m->pc,
+            (uintptr_t)m->pcz.p, bits(prm->rho), bits(prm->mu), bits(prm->period),
             bits(prm->C_I), bits(prm->beta_bf)};
   }
 
@@ -1238,7 +1323,12 @@ struct Solver {
   int update_state() {
     Workspace& w = m->ws;
     const double* tab = w.tab.as<double>();
-    if (binv) {
+    if (use_pc) {
+      HB_CHECK((hb::precond_apply<T, double>(m->pc, m->dm.n, sb->xvec.as<T>(), 4,
+                                             m->pcz.as<double>(), st)));
+      HB_CHECK(hb::vec_mul_dinv_add<double>(w.Sy.as<double>(), m->pcz.as<double>(), nullptr,
+                                            m->dm.dmask, m->dm.n, N, hb::NCH, 4, 1.0, st));
+    } else if (binv) {
       HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, sb->xvec.as<T>(), 4, w.dinv.as<double>(),
                                                  binv, 1, tab, w.Sv.as<double>(), nullptr,
                                                  nullptr, 0, st)));
@@ -1276,9 +1366,17 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
     if (N > 64) return fail(HB_ERR_ARG, "HB_PREC_NODE_TIME needs K <= 31");
     HB_CHECK(m->ws.binv.ensure(sizeof(double) * (size_t)m->dm.n * N * N));
     S.binv = m->ws.binv.as<double>();
+  } else if (opts->precond == HB_PREC_MEANFLOW) {
+    rc = ensure_precond(m, kCoarseMax, opts->amg_aggregation == 0, N);
+    if (rc) return rc;
+    S.use_pc = true;
   } else if (opts->precond != HB_PREC_JACOBI) {
     return fail(HB_ERR_ARG, "unknown preconditioner");
   }
+  const int amg_nu = opts->amg_sweeps > 0 ? opts->amg_sweeps : 2;
+  const int amg_cyc = opts->amg_cycles > 0 ? opts->amg_cycles : 1;
+  const double amg_w = opts->amg_weight > 0 ? opts->amg_weight : 0.7;
+  const double amg_g = opts->amg_coarse_weight > 0 ? opts->amg_coarse_weight : 0.7;
   Workspace& w = m->ws;
   const double* tab = w.tab.as<double>();
   HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab,
@@ -1310,6 +1408,28 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   const double ref = opts->r_ref > 0 ? opts->r_ref : rn;
   report->r_ref = ref;
   const double ser_ref = std::max(ref, rn);
+  // Pseudo-step control.  The first step follows switched evolution
+  // relaxation from max(reference, initial residual), so a start whose
+  // residual is already below the reference takes a larger step at once;
+  // later steps scale dt by the residual ratio of the accepted step (at
+  // least by dt_growth when the residual did not grow).  Globalisation: a
+  // step whose residual exceeds reject_ratio times the previous one (or is
+  // not finite) is damped, y + alpha delta with alpha = 1/2, 1/4, ... 1/64,
+  // until the residual falls below the previous one, and the trial with the
+  // smallest residual is kept (a smaller pseudo step would not help here:
+  // the pseudo-time term does not reach the pressure update); the next
+  // pseudo step is scaled by sqrt(alpha), never below 1/100 of the first.
+  const double reject = opts->reject_ratio == 0 ? 3.0 : opts->reject_ratio;
+  const double grow_min = opts->dt_growth > 0 ? opts->dt_growth : 1.0;
+  constexpr int kMaxHalve = 6;
+  double dt = std::min(dt0 * ser_ref / std::max(rn, 1e-300), dt_max);
+  const double dt_min = 0.01 * dt0;
+  const int64_t sy_len = m->dm.n * hb::NCH * N;
+  const size_t sy_bytes = sizeof(double) * (size_t)sy_len;
+  if (reject > 0) {
+    HB_CHECK(m->sb.sysave.ensure(sy_bytes));
+    HB_CHECK(m->sb.syfull.ensure(sy_bytes));
+  }
   int status = HB_ERR_NOCONV;
   int it = 0;
   for (;; ++it) {
@@ -1318,35 +1438,76 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
       break;
     }
     if (it >= opts->max_newton) break;
-    // switched evolution relaxation: the pseudo step grows as the residual
-    // falls below max(reference, initial residual), so a start whose
-    // residual is already below the reference takes larger steps at once
-    const double dt = std::min(dt0 * ser_ref / std::max(rn, 1e-300), dt_max);
     const double shift = opts->c1 * prm->rho / dt;
     const Phys pj = make_phys(prm, shift);
-    const int nc = S.binv ? 4 : 2;
-    HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), m->dm.n * nc * N, st));
-    HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), S.binv ? 1 : 0, st));
-    HB_CHECK(hb::jacobi_out(m->dm, N, nc, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
-    if (S.binv)
-      HB_CHECK(hb::block_factor(m->dm, N, w.dg.as<double>(), m->dm.mass, prm->rho, tab,
-                                w.binv.as<double>(), st));
+    if (S.use_pc) {
+      HB_CHECK(hb::precond_setup(m->pc, m->dm, pj, w.Sy.as<double>(), shift, amg_nu, amg_cyc,
+                                 amg_w, amg_g, st));
+    } else {
+      const int nc = S.binv ? 4 : 2;
+      HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), m->dm.n * nc * N, st));
+      HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), S.binv ? 1 : 0,
+                               st));
+      HB_CHECK(hb::jacobi_out(m->dm, N, nc, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
+      if (S.binv)
+        HB_CHECK(hb::block_factor(m->dm, N, w.dg.as<double>(), m->dm.mass, prm->rho, tab,
+                                  w.binv.as<double>(), st));
+    }
     int gi = 0;
     rc = S.gmres(r, shift, opts->gmres_eta, opts->max_gmres, gi);
     if (rc) return rc;
     report->gmres_iters += gi;
+    double* Sy = w.Sy.as<double>();
+    double* save = m->sb.sysave.as<double>();
+    double* full = m->sb.syfull.as<double>();
+    if (reject > 0) HB_CHECK(hipMemcpyAsync(save, Sy, sy_bytes, hipMemcpyDeviceToDevice, st));
     rc = S.update_state();
     if (rc) return rc;
     double rn_new = 0.0;
     rc = S.residual(r, rn_new);
     if (rc) return rc;
+    double alpha = 1.0;
+    if (reject > 0 && !(rn_new <= reject * rn)) {
+      // damped steps along the same direction; keep the best one
+      HB_CHECK(hipMemcpyAsync(full, Sy, sy_bytes, hipMemcpyDeviceToDevice, st));
+      double best = std::isfinite(rn_new) ? rn_new : HUGE_VAL, best_a = 1.0, a = 1.0;
+      for (int h = 0; h < kMaxHalve; ++h) {
+        a *= 0.5;
+        HB_CHECK(hb::vec_blend(Sy, save, full, sy_len, a, st));
+        double ra = 0.0;
+        rc = S.residual(r, ra);
+        if (rc) return rc;
+        if (std::isfinite(ra) && ra < best) {
+          best = ra;
+          best_a = a;
+        }
+        if (ra <= rn) break;
+      }
+      ++report->rejected;
+      if (best_a != a) {  // the last trial is not the best: restore the best
+        HB_CHECK(hb::vec_blend(Sy, save, full, sy_len, best_a, st));
+        rc = S.residual(r, rn_new);
+        if (rc) return rc;
+      } else {
+        rn_new = best;
+      }
+      alpha = best_a;
+    }
     if (!std::isfinite(rn_new)) {
       report->newton_iters = it + 1;
       return fail(HB_ERR_NAN, "non-finite residual");
     }
-    rn = rn_new;
     if (opts->verbose)
-      std::fprintf(stderr, "hb newton %d: |r| = %.3e  gmres %d  dt %.3e\n", it + 1, rn, gi, dt);
+      std::fprintf(stderr, "hb newton %d: |r| = %.3e  gmres %d  dt %.3e  alpha %.3g\n", it + 1,
+                   rn_new, gi, dt, alpha);
+    if (alpha < 1.0) {
+      dt = std::max(dt * std::sqrt(alpha), dt_min);
+    } else {
+      double f = rn / std::max(rn_new, 1e-300);
+      if (rn_new <= rn) f = std::max(f, grow_min);
+      dt = std::min(dt * std::max(f, 0.1), dt_max);
+    }
+    rn = rn_new;
   }
   report->newton_iters = it;
   report->r_final = rn;
@@ -1521,6 +1682,13 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
   if (opts->max_newton < 0 || opts->max_gmres < 1) return fail(HB_ERR_ARG, "bad iteration limits");
   if (!(opts->rtol > 0) || !(opts->gmres_eta > 0) || !(opts->cfl > 0) || !(opts->c1 >= 0))
     return fail(HB_ERR_ARG, "rtol, gmres_eta, cfl must be positive");
+  if (!std::isfinite(opts->reject_ratio) || !(opts->dt_growth >= 0) ||
+      !std::isfinite(opts->dt_growth) || (opts->reject_ratio > 0 && opts->reject_ratio < 1))
+    return fail(HB_ERR_ARG, "reject_ratio must be finite (0, < 0 or >= 1), dt_growth >= 0");
+  if (opts->amg_sweeps < 0 || opts->amg_cycles < 0 || !(opts->amg_weight >= 0) ||
+      opts->amg_weight > 1 || (opts->amg_aggregation != 0 && opts->amg_aggregation != 1) ||
+      !(opts->amg_coarse_weight >= 0) || opts->amg_coarse_weight > 2)
+    return fail(HB_ERR_ARG, "bad multigrid options");
   hb_mesh* m = const_cast<hb_mesh*>(mesh);
   hipStream_t st = (hipStream_t)stream;
   int rc = prepare(m, prm, bc, st);

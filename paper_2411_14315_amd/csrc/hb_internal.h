@@ -12,6 +12,31 @@ namespace hb {
 // Thread-local message returned by hb_last_error().
 void set_last_error(const std::string& msg);
 
+// Owning device array of T (grown on demand, freed on destruction).
+template <class T>
+struct DeviceArray {
+  T* p = nullptr;
+  size_t n = 0;
+  DeviceArray() = default;
+  DeviceArray(const DeviceArray&) = delete;
+  DeviceArray& operator=(const DeviceArray&) = delete;
+  DeviceArray(DeviceArray&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  ~DeviceArray() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t count) {
+    if (p && count <= n) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc((void**)&p, sizeof(T) * (count ? count : 1));
+    if (e == hipSuccess) n = count;
+    return e;
+  }
+  size_t bytes() const { return sizeof(T) * n; }
+};
+
 // Library-owned device view of a mesh (structure of arrays).
 struct DevMesh {
   int64_t n = 0;      // nodes
@@ -148,6 +173,36 @@ template <typename TU>
 hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const uint8_t* dmask,
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st);
 hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st);
+// y = a + alpha (b - a); y may alias a or b
+hipError_t vec_blend(double* y, const double* a, const double* b, int64_t L, double alpha,
+                     hipStream_t st);
+// Mean-flow modal preconditioner (hb_precond.hip): per-mode complex systems
+// of the sample-averaged frozen tangent, approximated by aggregation
+// multigrid V-cycles on the node graph.
+struct Precond;
+// pairwise = 1: aggregates from two passes of pairwise matching (up to 4
+// nodes); 0: a node and its free neighbours.
+hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int coarse_max,
+                          int pairwise, Precond** out);
+void precond_destroy(Precond* p);
+size_t precond_bytes(const Precond* p);
+// sizes[l] = nodes of level l (l < max); returns the number of levels
+int precond_levels(const Precond* p, int64_t* sizes, int max);
+// Coefficients at the state samples Sy ([n][7][N]) with pseudo-time mass
+// coefficient sigma; nu Jacobi sweeps (weight wj) before and after each
+// coarse correction (weight gamma), `cycles` V-cycles per application.
+hipError_t precond_setup(Precond* pc, const DevMesh& m, const Phys& p, const double* Sy,
+                         double sigma, int nu, int cycles, double wj, double gamma,
+                         hipStream_t st);
+// z [n][4][N] = M^-1 q, q with in_ch channels per node ([n][in_ch][N]).
+template <typename TQ, typename TZ>
+hipError_t precond_apply(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st);
+// z [n][4][N] = M q (the mean-flow operator itself, for checking).
+template <typename TQ, typename TZ>
+hipError_t precond_matvec(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st);
+// 1 in *flag_host if the coarsest-level inversion met a zero pivot (waits).
+hipError_t precond_singular(Precond* pc, int* flag_host, hipStream_t st);
+
 // Time-marching step: S[a][4+i][0] -= cu y_old[i][a] + ca a_old[i][a] (N = 1).
 hipError_t tm_history(const DevMesh& m, double* S, const double* y_old, const double* a_old,
                       double cu, double ca, hipStream_t st);

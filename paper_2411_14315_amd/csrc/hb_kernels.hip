@@ -1393,6 +1393,15 @@ k_copy_scaled(TD* __restrict__ d, const TS* __restrict__ x, int64_t L, double s)
     d[i] = (TD)(s * (double)x[i]);
 }
 
+// y = a + alpha (b - a) (damped Newton step between two states)
+__global__ void __launch_bounds__(BLK)
+k_blend(double* __restrict__ y, const double* __restrict__ a, const double* __restrict__ b,
+        int64_t L, double alpha) {
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < L; i += stride)
+    y[i] = a[i] + alpha * (b[i] - a[i]);
+}
+
 // y[a][c][s] += s * dinv[a][c<3?0:1][s] * u[a][c][s] for c < 4, skipping the
 // velocity entries of Dirichlet nodes.  y has nch_y channels per node.
 template <typename TU>
@@ -1640,6 +1649,12 @@ hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const ui
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st) {
   hipLaunchKernelGGL((k_mul_dinv_add<TU>), dim3(blocks_for(n * 4 * N)), dim3(BLK), 0, st, y, u,
                      dinv, dmask, n, N, nch_y, nch_u, s);
+  return hipGetLastError();
+}
+
+hipError_t vec_blend(double* y, const double* a, const double* b, int64_t L, double alpha,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_blend, dim3(stream_blocks(L)), dim3(BLK), 0, st, y, a, b, L, alpha);
   return hipGetLastError();
 }
 

@@ -1,0 +1,953 @@
+// Mean-flow modal preconditioner for the Newton-GMRES solve of the HB
+// equations (Section 2.3 of arXiv 2411.14315 preconditions its GMRES with the
+// Jacobi diagonal of the tangent P; this is a stronger, spatially coupled
+// replacement that changes iteration counts, not the root).
+//
+// The tangent of eq. Rmc with frozen advection and frozen tau (the paper's P
+// of eq. K_mat plus the Galerkin time term C of eq. ctangent and the
+// stabilisation's time terms that the paper drops) couples samples only
+// through H.  Replacing every time-diagonal coefficient by its mean over
+// the samples (the circulant projection of the operator in time) leaves an
+// operator that the DFT block-diagonalises: Fourier mode m (H -> i m w)
+// sees, per node pair (A, B),
+//
+//   velocity-velocity  kappa = K + sigma M + (m w)^2 rho T + i m w (rho M + Xs)   (x I3)
+//   velocity-pressure  g_i   = G_i - i m w G'_i
+//   pressure-velocity  d_j   = D_j + i m w D'_j
+//   pressure-pressure  l     = L
+//
+// with sample means of  K = int rho N_A u.grad N_B + mu grad N_A.grad N_B
+// + rho tau (u.grad N_A)(u.grad N_B);  G_i = -int d_i N_A N_B + tau
+// (u.grad N_A) d_i N_B;  D_j = int N_A d_j N_B + tau d_j N_A (u.grad N_B);
+// L = int tau/rho grad N_A.grad N_B  (eq. K_mat);  M = int N_A N_B;
+// T = int tau N_A N_B;  Xs = int rho tau ((u.grad N_A) N_B - N_A (u.grad N_B));
+// G'_i = int tau N_A d_i N_B;  D'_i = int tau d_i N_A N_B;  sigma = the
+// pseudo-time mass coefficient.  Dirichlet velocity rows are identity and
+// Dirichlet velocity columns are dropped.
+//
+// Each mode's complex system is approximated by V-cycles of an aggregation
+// multigrid on the node graph: aggregates from two passes of pairwise
+// matching (or of a node and its free neighbours), piecewise-constant
+// transfer with a weighted coarse correction, Galerkin coarse operators (the 17
+// coefficient fields above are summed over aggregate pairs, so every level
+// has the same form), damped block-Jacobi smoothing with the closed-form
+// inverse of the 4 x 4 nodal block, and a dense complex inverse on the
+// coarsest level.  All K+1 modes are processed by every launch: the matrix
+// coefficients are read once per node pair and applied to the K+1 mode
+// vectors of the neighbour.
+#include "hb_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <memory>
+#include <vector>
+
+namespace hb {
+
+namespace {
+
+constexpr int PBLK = 256;
+// coefficient fields per node pair (stride PC_NF doubles)
+enum {
+  F_K = 0, F_M = 1, F_T = 2, F_XS = 3, F_G = 4, F_D = 7, F_GP = 10, F_DP = 13, F_L = 16,
+  PC_NFIELDS = 17, PC_NF = 18
+};
+constexpr double QA_ = 0.58541019662496845446137605030969;
+constexpr double QB_ = 0.13819660112501051517954131656344;
+
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// Position of column c in row r of a CSR graph with sorted columns.
+__device__ __forceinline__ int64_t csr_find(const int32_t* __restrict__ rowptr,
+                                            const int32_t* __restrict__ col, int32_t r,
+                                            int32_t c) {
+  int lo = rowptr[r], hi = rowptr[r + 1] - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (col[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Fine-level coefficients: one lane per tetrahedron.  Sample means of the
+// quadrature-point quantities tau, tau u, tau u u^T and u are formed first
+// (13 per quadrature point); every node pair's 17 fields follow from them
+// and are added to the pair's CSR entry.
+__global__ void __launch_bounds__(PBLK)
+k_pc_assemble(int64_t ne, int64_t n, int N, const int32_t* __restrict__ tets,
+              const double* __restrict__ geo, const double* __restrict__ Sy,
+              const uint8_t* __restrict__ dmask, const int32_t* __restrict__ rowptr,
+              const int32_t* __restrict__ col, double* __restrict__ val, Phys p) {
+  const int64_t t = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (t >= ne) return;
+  int32_t a[4];
+#pragma unroll
+  for (int A = 0; A < 4; ++A) a[A] = tets[A * ne + t];
+  double g[4][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g[1][i] = geo[(GEO_G1 + i) * ne + t];
+    g[2][i] = geo[(GEO_G2 + i) * ne + t];
+    g[3][i] = geo[(GEO_G3 + i) * ne + t];
+    g[0][i] = geo[(GEO_G0 + i) * ne + t];
+  }
+  const double V = geo[GEO_V * ne + t];
+  const double x00 = geo[GEO_XI00 * ne + t], x01 = geo[GEO_XI01 * ne + t],
+               x02 = geo[GEO_XI02 * ne + t], x11 = geo[GEO_XI11 * ne + t],
+               x12 = geo[GEO_XI12 * ne + t], x22 = geo[GEO_XI22 * ne + t];
+  const double kap0 = p.C_I * p.nu * p.nu * geo[GEO_XIXI * ne + t] + p.tau_add;
+  // per quadrature point q: tau, tau u (3), tau u u^T (6: 00 01 02 11 12 22), u (3)
+  double mt[4], mtu[4][3], mtuu[4][6], mu_[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    mt[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) mtu[q][i] = mu_[q][i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mtuu[q][i] = 0.0;
+  }
+  for (int s = 0; s < N; ++s) {
+    double u[4][3];
+#pragma unroll
+    for (int A = 0; A < 4; ++A)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) u[A][i] = Sy[((int64_t)a[A] * NCH + i) * N + s];
+    double usum[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) usum[i] = u[0][i] + u[1][i] + u[2][i] + u[3][i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double uq[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) uq[i] = QB_ * usum[i] + (QA_ - QB_) * u[q][i];
+      const double kap = uq[0] * (x00 * uq[0] + x01 * uq[1] + x02 * uq[2]) +
+                         uq[1] * (x01 * uq[0] + x11 * uq[1] + x12 * uq[2]) +
+                         uq[2] * (x02 * uq[0] + x12 * uq[1] + x22 * uq[2]) + kap0;
+      const double tau = 1.0 / sqrt(kap);
+      mt[q] += tau;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        mtu[q][i] += tau * uq[i];
+        mu_[q][i] += uq[i];
+      }
+      mtuu[q][0] += tau * uq[0] * uq[0];
+      mtuu[q][1] += tau * uq[0] * uq[1];
+      mtuu[q][2] += tau * uq[0] * uq[2];
+      mtuu[q][3] += tau * uq[1] * uq[1];
+      mtuu[q][4] += tau * uq[1] * uq[2];
+      mtuu[q][5] += tau * uq[2] * uq[2];
+    }
+  }
+  const double wq = 0.25 * V / (double)N;  // quadrature weight and sample mean
+  const double rho = p.rho;
+  bool dir[4];
+#pragma unroll
+  for (int A = 0; A < 4; ++A) dir[A] = dmask[a[A]] != 0;
+  for (int A = 0; A < 4; ++A) {
+    for (int B = 0; B < 4; ++B) {
+      double f[PC_NFIELDS];
+#pragma unroll
+      for (int k = 0; k < PC_NFIELDS; ++k) f[k] = 0.0;
+      const double gg = g[A][0] * g[B][0] + g[A][1] * g[B][1] + g[A][2] * g[B][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double NA = A == q ? QA_ : QB_;
+        const double NB = B == q ? QA_ : QB_;
+        const double ucB = mu_[q][0] * g[B][0] + mu_[q][1] * g[B][1] + mu_[q][2] * g[B][2];
+        const double tcA = mtu[q][0] * g[A][0] + mtu[q][1] * g[A][1] + mtu[q][2] * g[A][2];
+        const double tcB = mtu[q][0] * g[B][0] + mtu[q][1] * g[B][1] + mtu[q][2] * g[B][2];
+        const double* T6 = mtuu[q];
+        const double tuuB0 = T6[0] * g[B][0] + T6[1] * g[B][1] + T6[2] * g[B][2];
+        const double tuuB1 = T6[1] * g[B][0] + T6[3] * g[B][1] + T6[4] * g[B][2];
+        const double tuuB2 = T6[2] * g[B][0] + T6[4] * g[B][1] + T6[5] * g[B][2];
+        const double supg = g[A][0] * tuuB0 + g[A][1] * tuuB1 + g[A][2] * tuuB2;
+        f[F_K] += wq * rho * (NA * ucB + supg);
+        f[F_T] += wq * mt[q] * NA * NB;
+        f[F_XS] += wq * rho * (tcA * NB - NA * tcB);
+        f[F_L] += wq * mt[q] * gg / rho;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          f[F_G + i] += wq * (-(double)N * g[A][i] * NB + tcA * g[B][i]);
+          f[F_D + i] += wq * ((double)N * NA * g[B][i] + tcB * g[A][i]);
+          f[F_GP + i] += wq * mt[q] * NA * g[B][i];
+          f[F_DP + i] += wq * mt[q] * g[A][i] * NB;
+        }
+      }
+      f[F_K] += p.mu * V * gg;
+      f[F_M] = V * (A == B ? 2.0 : 1.0) / 20.0;
+      if (dir[A]) {  // Dirichlet velocity row
+        f[F_K] = f[F_M] = f[F_T] = f[F_XS] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[F_G + i] = f[F_GP + i] = 0.0;
+      }
+      if (dir[B]) {  // Dirichlet velocity column
+        f[F_K] = f[F_M] = f[F_T] = f[F_XS] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[F_D + i] = f[F_DP + i] = 0.0;
+      }
+      double* v = val + csr_find(rowptr, col, a[A], a[B]) * PC_NF;
+#pragma unroll
+      for (int k = 0; k < PC_NFIELDS; ++k)
+        if (f[k] != 0.0) unsafeAtomicAdd(v + k, f[k]);
+    }
+  }
+}
+
+// Identity velocity block on the diagonal of Dirichlet rows.
+__global__ void __launch_bounds__(PBLK)
+k_pc_dirichlet(int64_t n, const uint8_t* __restrict__ dmask, const int32_t* __restrict__ diag,
+               double* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (i >= n || !dmask[i]) return;
+  val[(int64_t)diag[i] * PC_NF + F_K] = 1.0;
+}
+
+// Galerkin coarse coefficients: each coarse entry sums the fine entries of
+// its aggregate pair (a gather over a precomputed list: no atomics).
+__global__ void __launch_bounds__(PBLK)
+k_pc_galerkin(int64_t nnz_c, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gsrc,
+              const double* __restrict__ vf, double* __restrict__ vc) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= nnz_c * PC_NFIELDS) return;
+  const int64_t k = gid / PC_NFIELDS;
+  const int f = (int)(gid - k * PC_NFIELDS);
+  double s = 0.0;
+  for (int j = gptr[k]; j < gptr[k + 1]; ++j) s += vf[(int64_t)gsrc[j] * PC_NF + f];
+  vc[k * PC_NF + f] = s;
+}
+
+struct Coef {
+  double sigma, rho, omega;
+  int nm;
+};
+
+// The mode-m coefficients of one node pair.
+struct PairOp {
+  cplx kap, g[3], d[3];
+  double l;
+};
+__device__ __forceinline__ PairOp pair_op(const double* __restrict__ v, const Coef& c, double s) {
+  PairOp o;
+  o.kap = {v[F_K] + c.sigma * v[F_M] + s * s * c.rho * v[F_T], s * (c.rho * v[F_M] + v[F_XS])};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o.g[i] = {v[F_G + i], -s * v[F_GP + i]};
+    o.d[i] = {v[F_D + i], s * v[F_DP + i]};
+  }
+  o.l = v[F_L];
+  return o;
+}
+
+// Complex vectors: [node][mode][4][re, im].
+__device__ __forceinline__ void load4(const double* __restrict__ x, int64_t idx, cplx out[4]) {
+  const double* p = x + idx * 8;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) out[f] = {p[2 * f], p[2 * f + 1]};
+}
+__device__ __forceinline__ void store4(double* __restrict__ x, int64_t idx, const cplx v[4]) {
+  double* p = x + idx * 8;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    p[2 * f] = v[f].re;
+    p[2 * f + 1] = v[f].im;
+  }
+}
+
+// Row operation on all modes, one lane per (node, mode):
+//   OP 0: y = A x;  OP 1: y = b - A x;
+//   OP 2: y = x + w D^-1 (b - A x) (x = NULL: y = w D^-1 b), D the nodal block.
+template <int OP>
+__global__ void __launch_bounds__(PBLK)
+k_pc_rows(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+          const int32_t* __restrict__ diag, const double* __restrict__ val, Coef c,
+          const double* __restrict__ b, const double* __restrict__ x, double* __restrict__ y,
+          double wj) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= n * c.nm) return;
+  const int64_t i = gid / c.nm;
+  const int m = (int)(gid - i * c.nm);
+  const double s = m * c.omega;
+  cplx acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  if (x) {
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      const int64_t j = col[k];
+      const PairOp o = pair_op(val + (int64_t)k * PC_NF, c, s);
+      cplx xj[4];
+      load4(x, j * c.nm + m, xj);
+#pragma unroll
+      for (int f = 0; f < 3; ++f) acc[f] = cadd(acc[f], cadd(cmul(o.kap, xj[f]), cmul(o.g[f], xj[3])));
+      acc[3] = cadd(acc[3], cadd(cadd(cmul(o.d[0], xj[0]), cmul(o.d[1], xj[1])),
+                                 cadd(cmul(o.d[2], xj[2]), {o.l * xj[3].re, o.l * xj[3].im})));
+    }
+  }
+  if (OP == 0) {
+    store4(y, gid, acc);
+    return;
+  }
+  cplx r[4];
+  load4(b, gid, r);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) r[f] = csub(r[f], acc[f]);
+  if (OP == 1) {
+    store4(y, gid, r);
+    return;
+  }
+  // block solve [kap I, g; d^T, l] e = r
+  const PairOp o = pair_op(val + (int64_t)diag[i] * PC_NF, c, s);
+  cplx sp = r[3], den = {o.l, 0.0};
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    sp = csub(sp, cdiv(cmul(o.d[f], r[f]), o.kap));
+    den = csub(den, cdiv(cmul(o.d[f], o.g[f]), o.kap));
+  }
+  cplx e[4];
+  e[3] = cdiv(sp, den);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) e[f] = cdiv(csub(r[f], cmul(o.g[f], e[3])), o.kap);
+  cplx out[4];
+  if (x) load4(x, gid, out);
+  else out[0] = out[1] = out[2] = out[3] = {0.0, 0.0};
+#pragma unroll
+  for (int f = 0; f < 4; ++f) out[f] = {out[f].re + wj * e[f].re, out[f].im + wj * e[f].im};
+  store4(y, gid, out);
+}
+
+// bc[I] = sum of r over the members of aggregate I (all modes).
+__global__ void __launch_bounds__(PBLK)
+k_pc_restrict(int64_t nc, int nm, const int32_t* __restrict__ mptr,
+              const int32_t* __restrict__ mem, const double* __restrict__ r,
+              double* __restrict__ bc) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= nc * nm * 8) return;
+  const int64_t I = gid / (nm * 8);
+  const int k = (int)(gid - I * nm * 8);
+  double s = 0.0;
+  for (int j = mptr[I]; j < mptr[I + 1]; ++j) s += r[(int64_t)mem[j] * nm * 8 + k];
+  bc[gid] = s;
+}
+
+// x[i] += gamma xc[agg[i]] (all modes).
+__global__ void __launch_bounds__(PBLK)
+k_pc_prolong(int64_t n, int nm, const int32_t* __restrict__ agg, const double* __restrict__ xc,
+             double* __restrict__ x, double gamma) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= n * nm * 8) return;
+  const int64_t i = gid / (nm * 8);
+  const int k = (int)(gid - i * nm * 8);
+  x[gid] += gamma * xc[(int64_t)agg[i] * nm * 8 + k];
+}
+
+// Dense coarsest-level matrices, one per mode: A[m][4I+a][4J+b] (complex,
+// row-major, D = 4 nc), filled from the CSR coefficients.  A must be zero.
+__global__ void __launch_bounds__(PBLK)
+k_pc_dense(int64_t nc, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+           const double* __restrict__ val, Coef c, double* __restrict__ A) {
+  const int64_t nnz = rowptr[nc];
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= nnz * c.nm) return;
+  const int64_t k = gid / c.nm;
+  const int m = (int)(gid - k * c.nm);
+  // row of entry k
+  int lo = 0, hi = (int)nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rowptr[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t I = lo, J = col[k];
+  const int64_t D = 4 * nc;
+  const PairOp o = pair_op(val + k * PC_NF, c, m * c.omega);
+  double* Am = A + (int64_t)m * D * D * 2;
+  auto put = [&](int64_t r, int64_t cc, cplx v) {
+    Am[(r * D + cc) * 2] = v.re;
+    Am[(r * D + cc) * 2 + 1] = v.im;
+  };
+  for (int f = 0; f < 3; ++f) {
+    put(4 * I + f, 4 * J + f, o.kap);
+    put(4 * I + f, 4 * J + 3, o.g[f]);
+    put(4 * I + 3, 4 * J + f, o.d[f]);
+  }
+  put(4 * I + 3, 4 * J + 3, {o.l, 0.0});
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting of one D x D
+// complex matrix per workgroup (mode = blockIdx.x); W holds [D][2D]
+// (matrix | identity) and receives [I | A^-1]; the inverse is copied to Ainv.
+__global__ void __launch_bounds__(PBLK)
+k_pc_invert(int D, const double* __restrict__ A, double* __restrict__ W,
+            double* __restrict__ Ainv, int* __restrict__ singular) {
+  const int m = blockIdx.x;
+  const double* Am = A + (int64_t)m * D * D * 2;
+  double* Wm = W + (int64_t)m * D * 2 * D * 2;
+  const int W2 = 2 * D;
+  for (int64_t e = threadIdx.x; e < (int64_t)D * W2; e += PBLK) {
+    const int r = (int)(e / W2), cc = (int)(e - (int64_t)r * W2);
+    double re = 0.0, im = 0.0;
+    if (cc < D) {
+      re = Am[((int64_t)r * D + cc) * 2];
+      im = Am[((int64_t)r * D + cc) * 2 + 1];
+    } else if (cc - D == r) {
+      re = 1.0;
+    }
+    Wm[e * 2] = re;
+    Wm[e * 2 + 1] = im;
+  }
+  __shared__ double smax[PBLK];
+  __shared__ int sidx[PBLK];
+  __shared__ double piv[2];
+  __syncthreads();
+  for (int k = 0; k < D; ++k) {
+    // pivot search in column k, rows k..D-1
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + threadIdx.x; r < D; r += PBLK) {
+      const double* w = Wm + ((int64_t)r * W2 + k) * 2;
+      const double a = w[0] * w[0] + w[1] * w[1];
+      if (a > best) {
+        best = a;
+        bi = r;
+      }
+    }
+    smax[threadIdx.x] = best;
+    sidx[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = PBLK / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off && smax[threadIdx.x + off] > smax[threadIdx.x]) {
+        smax[threadIdx.x] = smax[threadIdx.x + off];
+        sidx[threadIdx.x] = sidx[threadIdx.x + off];
+      }
+      __syncthreads();
+    }
+    const int pr = sidx[0];
+    if (!(smax[0] > 0.0)) {
+      if (threadIdx.x == 0) atomicOr(singular, 1);
+      return;  // uniform across the workgroup
+    }
+    // swap rows k and pr
+    if (pr != k)
+      for (int cc = threadIdx.x; cc < W2; cc += PBLK) {
+        double* a = Wm + ((int64_t)k * W2 + cc) * 2;
+        double* b2 = Wm + ((int64_t)pr * W2 + cc) * 2;
+        const double t0 = a[0], t1 = a[1];
+        a[0] = b2[0];
+        a[1] = b2[1];
+        b2[0] = t0;
+        b2[1] = t1;
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double* w = Wm + ((int64_t)k * W2 + k) * 2;
+      const double d = w[0] * w[0] + w[1] * w[1];
+      piv[0] = w[0] / d;
+      piv[1] = -w[1] / d;
+    }
+    __syncthreads();
+    const cplx ip = {piv[0], piv[1]};
+    for (int cc = threadIdx.x; cc < W2; cc += PBLK) {
+      double* a = Wm + ((int64_t)k * W2 + cc) * 2;
+      const cplx v = cmul({a[0], a[1]}, ip);
+      a[0] = v.re;
+      a[1] = v.im;
+    }
+    __syncthreads();
+    // eliminate column k from every other row
+    for (int64_t e = threadIdx.x; e < (int64_t)D * W2; e += PBLK) {
+      const int r = (int)(e / W2), cc = (int)(e - (int64_t)r * W2);
+      if (r == k || cc == k) continue;
+      const double* fr = Wm + ((int64_t)r * W2 + k) * 2;
+      const double* pk = Wm + ((int64_t)k * W2 + cc) * 2;
+      double* a = Wm + e * 2;
+      const cplx v = csub({a[0], a[1]}, cmul({fr[0], fr[1]}, {pk[0], pk[1]}));
+      a[0] = v.re;
+      a[1] = v.im;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < D; r += PBLK)
+      if (r != k) {
+        double* a = Wm + ((int64_t)r * W2 + k) * 2;
+        a[0] = 0.0;
+        a[1] = 0.0;
+      }
+    __syncthreads();
+  }
+  double* Im = Ainv + (int64_t)m * D * D * 2;
+  for (int64_t e = threadIdx.x; e < (int64_t)D * D; e += PBLK) {
+    const int r = (int)(e / D), cc = (int)(e - (int64_t)r * D);
+    Im[e * 2] = Wm[((int64_t)r * W2 + D + cc) * 2];
+    Im[e * 2 + 1] = Wm[((int64_t)r * W2 + D + cc) * 2 + 1];
+  }
+}
+
+// x = Ainv_m b on the coarsest level; one lane per (mode, row).
+__global__ void __launch_bounds__(PBLK)
+k_pc_dense_apply(int64_t nc, int nm, const double* __restrict__ Ainv,
+                 const double* __restrict__ b, double* __restrict__ x) {
+  const int64_t D = 4 * nc;
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= D * nm) return;
+  const int m = (int)(gid / D);
+  const int64_t r = gid - (int64_t)m * D;
+  const double* Ar = Ainv + ((int64_t)m * D * D + r * D) * 2;
+  double re = 0.0, im = 0.0;
+  for (int64_t cc = 0; cc < D; ++cc) {
+    const int64_t J = cc >> 2;
+    const int f = (int)(cc & 3);
+    const double* bv = b + ((J * nm + m) * 4 + f) * 2;
+    re += Ar[cc * 2] * bv[0] - Ar[cc * 2 + 1] * bv[1];
+    im += Ar[cc * 2] * bv[1] + Ar[cc * 2 + 1] * bv[0];
+  }
+  const int64_t I = r >> 2;
+  const int f = (int)(r & 3);
+  double* xv = x + ((I * nm + m) * 4 + f) * 2;
+  xv[0] = re;
+  xv[1] = im;
+}
+
+// Samples -> modes: b[a][m][f] = (1/N) sum_s q[a][f][s] e^{-2 pi i m s / N}
+// (m = 0..K), one lane per (node, mode); q has in_ch channels per node.
+template <typename TQ>
+__global__ void __launch_bounds__(PBLK)
+k_pc_to_modes(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
+              const double* __restrict__ cs, double* __restrict__ b) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= n * nm) return;
+  const int64_t a = gid / nm;
+  const int m = (int)(gid - a * nm);
+  cplx out[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double re = 0.0, im = 0.0;
+    const TQ* qa = q + (a * in_ch + f) * N;
+    for (int s = 0; s < N; ++s) {
+      const double v = (double)qa[s];
+      re += v * cs[(m * N + s) * 2];
+      im -= v * cs[(m * N + s) * 2 + 1];
+    }
+    out[f] = {re / N, im / N};
+  }
+  store4(b, gid, out);
+}
+
+// Modes -> samples: z[a][f][s] = Re x_0 + 2 sum_{m>=1} Re(x_m e^{2 pi i m s/N}),
+// one lane per (node, field, sample).
+template <typename TZ>
+__global__ void __launch_bounds__(PBLK)
+k_pc_from_modes(int64_t n, int N, int nm, const double* __restrict__ x,
+                const double* __restrict__ cs, TZ* __restrict__ z) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= n * 4 * N) return;
+  const int64_t a = gid / (4 * N);
+  const int r = (int)(gid - a * 4 * N);
+  const int f = r / N;
+  const int s = r - f * N;
+  double v = x[((a * nm + 0) * 4 + f) * 2];
+  for (int m = 1; m < nm; ++m) {
+    const double* xm = x + ((a * nm + m) * 4 + f) * 2;
+    v += 2.0 * (xm[0] * cs[(m * N + s) * 2] - xm[1] * cs[(m * N + s) * 2 + 1]);
+  }
+  z[gid] = (TZ)v;
+}
+
+inline unsigned nblk(int64_t work) { return (unsigned)((work + PBLK - 1) / PBLK); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- hierarchy
+
+struct PcLevel {
+  int64_t n = 0, nnz = 0;
+  DeviceArray<int32_t> rowptr, col, diag;
+  DeviceArray<double> val;
+  // transfer to the next level: aggregate of each node, members of each
+  // coarse node, and the fine entries of each coarse entry
+  DeviceArray<int32_t> agg, mptr, mem, gptr, gsrc;
+  DeviceArray<double> x, x2, b, r;
+};
+
+struct Precond {
+  std::vector<PcLevel> lv;
+  int nm = 0;       // modes (K + 1) the vectors are sized for
+  int N = 0;
+  DeviceArray<double> cs;            // [nm][N] (cos, sin) of 2 pi m s / N
+  DeviceArray<double> dense, work, inv;  // coarsest level
+  DeviceArray<int> flag;
+  int64_t dense_D = 0;
+  int nu = 2;
+  int cycles = 1;
+  double wj = 0.7;
+  double gamma = 1.0;  // weight of the coarse-level correction
+  Coef coef{};
+  size_t bytes() const {
+    size_t b = cs.bytes() + dense.bytes() + work.bytes() + inv.bytes();
+    for (const auto& l : lv)
+      b += l.rowptr.bytes() + l.col.bytes() + l.diag.bytes() + l.val.bytes() + l.agg.bytes() +
+           l.mptr.bytes() + l.mem.bytes() + l.gptr.bytes() + l.gsrc.bytes() + l.x.bytes() +
+           l.x2.bytes() + l.b.bytes() + l.r.bytes();
+    return b;
+  }
+};
+
+void precond_destroy(Precond* p) { delete p; }
+size_t precond_bytes(const Precond* p) { return p ? p->bytes() : 0; }
+int precond_levels(const Precond* p, int64_t* sizes, int max) {
+  if (!p) return 0;
+  const int L = (int)std::min<size_t>(p->lv.size(), (size_t)max);
+  for (int i = 0; i < L; ++i) sizes[i] = p->lv[i].n;
+  return (int)p->lv.size();
+}
+
+namespace {
+
+struct HostGraph {
+  std::vector<int32_t> rowptr, col;
+};
+
+// Node graph (with self loops, sorted columns) of a tetrahedral mesh.
+HostGraph node_graph(int64_t n, int64_t ne, const std::vector<int32_t>& tets_soa) {
+  std::vector<int32_t> tptr(n + 1, 0), tl(4 * ne);
+  for (int64_t k = 0; k < 4 * ne; ++k) ++tptr[tets_soa[k] + 1];
+  for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+  {
+    std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t A = 0; A < 4; ++A)
+      for (int64_t t = 0; t < ne; ++t) tl[fill[tets_soa[A * ne + t]]++] = (int32_t)t;
+  }
+  HostGraph g;
+  g.rowptr.assign(n + 1, 0);
+  g.col.reserve(16 * n);
+  std::vector<int32_t> nb;
+  for (int64_t i = 0; i < n; ++i) {
+    nb.clear();
+    nb.push_back((int32_t)i);
+    for (int k = tptr[i]; k < tptr[i + 1]; ++k)
+      for (int A = 0; A < 4; ++A) nb.push_back(tets_soa[A * ne + tl[k]]);
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    g.col.insert(g.col.end(), nb.begin(), nb.end());
+    g.rowptr[i + 1] = (int32_t)g.col.size();
+  }
+  return g;
+}
+
+// Greedy aggregation: a node whose neighbours are all free starts an
+// aggregate with them; the remaining nodes join a neighbouring aggregate,
+// or form one of their own.
+int64_t aggregate(const HostGraph& g, std::vector<int32_t>& agg) {
+  const int64_t n = (int64_t)g.rowptr.size() - 1;
+  agg.assign(n, -1);
+  int64_t na = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free = true;
+    for (int k = g.rowptr[i]; k < g.rowptr[i + 1] && free; ++k) free = agg[g.col[k]] < 0;
+    if (!free) continue;
+    for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k) agg[g.col[k]] = (int32_t)na;
+    ++na;
+  }
+  std::vector<int32_t> pass2(agg);
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k)
+      if (agg[g.col[k]] >= 0) {
+        pass2[i] = agg[g.col[k]];
+        break;
+      }
+  }
+  agg.swap(pass2);
+  for (int64_t i = 0; i < n; ++i)
+    if (agg[i] < 0) agg[i] = (int32_t)na++;
+  return na;
+}
+
+// Members of each aggregate (CSR) and the aggregated graph.
+void coarsen_graph(const HostGraph& g, const std::vector<int32_t>& agg, int64_t na,
+                   std::vector<int32_t>& mptr, std::vector<int32_t>& mem, HostGraph& gc) {
+  const int64_t nl = (int64_t)g.rowptr.size() - 1;
+  mptr.assign(na + 1, 0);
+  mem.resize(nl);
+  for (int64_t i = 0; i < nl; ++i) ++mptr[agg[i] + 1];
+  for (int64_t I = 0; I < na; ++I) mptr[I + 1] += mptr[I];
+  {
+    std::vector<int32_t> fill(mptr.begin(), mptr.end() - 1);
+    for (int64_t i = 0; i < nl; ++i) mem[fill[agg[i]]++] = (int32_t)i;
+  }
+  gc.rowptr.assign(na + 1, 0);
+  gc.col.clear();
+  std::vector<int32_t> nb;
+  for (int64_t I = 0; I < na; ++I) {
+    nb.clear();
+    for (int j = mptr[I]; j < mptr[I + 1]; ++j) {
+      const int32_t i = mem[j];
+      for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k) nb.push_back(agg[g.col[k]]);
+    }
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    gc.col.insert(gc.col.end(), nb.begin(), nb.end());
+    gc.rowptr[I + 1] = (int32_t)gc.col.size();
+  }
+}
+
+// One pass of pairwise matching: each node in turn is paired with its first
+// unmatched neighbour (or left alone); pairs are numbered in order.
+int64_t match_pairs(const HostGraph& g, std::vector<int32_t>& agg) {
+  const int64_t n = (int64_t)g.rowptr.size() - 1;
+  std::vector<int32_t> mate(n, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    if (mate[i] >= 0) continue;
+    mate[i] = (int32_t)i;
+    for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k) {
+      const int32_t j = g.col[k];
+      if (j != i && mate[j] < 0) {
+        mate[i] = j;
+        mate[j] = (int32_t)i;
+        break;
+      }
+    }
+  }
+  agg.assign(n, -1);
+  int64_t na = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (agg[i] < 0) {
+      agg[i] = (int32_t)na;
+      agg[mate[i]] = (int32_t)na;
+      ++na;
+    }
+  return na;
+}
+
+// Two passes of pairwise matching: aggregates of up to four nodes.
+int64_t aggregate_pairs(const HostGraph& g, std::vector<int32_t>& agg) {
+  std::vector<int32_t> a1, a2, mptr, mem;
+  const int64_t n1 = match_pairs(g, a1);
+  HostGraph g1;
+  coarsen_graph(g, a1, n1, mptr, mem, g1);
+  const int64_t n2 = match_pairs(g1, a2);
+  agg.resize(a1.size());
+  for (size_t i = 0; i < a1.size(); ++i) agg[i] = a2[a1[i]];
+  return n2;
+}
+
+template <typename T>
+hipError_t upload(DeviceArray<T>& d, const std::vector<T>& h) {
+  hipError_t e = d.ensure(h.size());
+  if (e != hipSuccess) return e;
+  if (!h.empty()) e = hipMemcpy(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+}  // namespace
+
+hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int coarse_max,
+                          int pairwise, Precond** out) {
+  *out = nullptr;
+  std::vector<int32_t> T(4 * ne);
+  hipError_t e = hipMemcpy(T.data(), tets_dev, sizeof(int32_t) * 4 * ne, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  std::unique_ptr<Precond> pc(new Precond());
+  HostGraph g = node_graph(n, ne, T);
+  T.clear();
+  T.shrink_to_fit();
+  for (int level = 0;; ++level) {
+    pc->lv.emplace_back();
+    PcLevel& L = pc->lv.back();
+    const int64_t nl = (int64_t)g.rowptr.size() - 1;
+    L.n = nl;
+    L.nnz = g.rowptr[nl];
+    std::vector<int32_t> diag(nl);
+    for (int64_t i = 0; i < nl; ++i)
+      for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k)
+        if (g.col[k] == i) diag[i] = k;
+    if ((e = upload(L.rowptr, g.rowptr)) || (e = upload(L.col, g.col)) || (e = upload(L.diag, diag)))
+      return e;
+    if ((e = L.val.ensure((size_t)L.nnz * PC_NF))) return e;
+    if (nl <= coarse_max || level >= 15) break;
+    std::vector<int32_t> agg, mptr, mem;
+    const int64_t na = pairwise ? aggregate_pairs(g, agg) : aggregate(g, agg);
+    if (na > (nl * 9) / 10) break;  // aggregation no longer coarsens
+    HostGraph gc;
+    coarsen_graph(g, agg, na, mptr, mem, gc);
+    // fine entries of every coarse entry
+    const int64_t nnzc = gc.rowptr[na];
+    std::vector<int32_t> cmap(L.nnz), gptr(nnzc + 1, 0), gsrc(L.nnz);
+    for (int64_t i = 0; i < nl; ++i) {
+      const int32_t I = agg[i];
+      const int32_t* b0 = gc.col.data() + gc.rowptr[I];
+      const int32_t* b1 = gc.col.data() + gc.rowptr[I + 1];
+      for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k) {
+        const int32_t J = agg[g.col[k]];
+        cmap[k] = (int32_t)((std::lower_bound(b0, b1, J) - gc.col.data()));
+        ++gptr[cmap[k] + 1];
+      }
+    }
+    for (int64_t k = 0; k < nnzc; ++k) gptr[k + 1] += gptr[k];
+    {
+      std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
+      for (int64_t k = 0; k < L.nnz; ++k) gsrc[fill[cmap[k]]++] = (int32_t)k;
+    }
+    if ((e = upload(L.agg, agg)) || (e = upload(L.mptr, mptr)) || (e = upload(L.mem, mem)) ||
+        (e = upload(L.gptr, gptr)) || (e = upload(L.gsrc, gsrc)))
+      return e;
+    g = std::move(gc);
+  }
+  const int64_t nc = pc->lv.back().n;
+  pc->dense_D = 4 * nc;
+  if ((e = pc->flag.ensure(1))) return e;
+  *out = pc.release();
+  return hipSuccess;
+}
+
+namespace {
+
+// Vectors and trigonometric table for K + 1 modes.
+hipError_t ensure_modes(Precond* pc, int N) {
+  const int nm = (N - 1) / 2 + 1;
+  if (pc->nm == nm && pc->N == N) return hipSuccess;
+  hipError_t e;
+  for (auto& L : pc->lv) {
+    const size_t len = (size_t)L.n * nm * 8;
+    if ((e = L.x.ensure(len)) || (e = L.x2.ensure(len)) || (e = L.b.ensure(len)) ||
+        (e = L.r.ensure(len)))
+      return e;
+  }
+  std::vector<double> cs((size_t)nm * N * 2);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int m = 0; m < nm; ++m)
+    for (int s = 0; s < N; ++s) {
+      const double th = two_pi * (double)((m * s) % N) / (double)N;
+      cs[(m * N + s) * 2] = std::cos(th);
+      cs[(m * N + s) * 2 + 1] = std::sin(th);
+    }
+  if ((e = upload(pc->cs, cs))) return e;
+  const int64_t D = pc->dense_D;
+  if ((e = pc->dense.ensure((size_t)nm * D * D * 2)) || (e = pc->inv.ensure((size_t)nm * D * D * 2)) ||
+      (e = pc->work.ensure((size_t)nm * D * 2 * D * 2)))
+    return e;
+  pc->nm = nm;
+  pc->N = N;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t precond_setup(Precond* pc, const DevMesh& m, const Phys& p, const double* Sy,
+                         double sigma, int nu, int cycles, double wj, double gamma,
+                         hipStream_t st) {
+  hipError_t e = ensure_modes(pc, p.N);
+  if (e != hipSuccess) return e;
+  pc->nu = nu;
+  pc->cycles = cycles;
+  pc->wj = wj;
+  pc->gamma = gamma;
+  pc->coef = {sigma, p.rho, p.omega, pc->nm};
+  PcLevel& F = pc->lv[0];
+  if ((e = hipMemsetAsync(F.val.p, 0, F.val.bytes(), st))) return e;
+  hipLaunchKernelGGL(k_pc_assemble, dim3(nblk(m.ne)), dim3(PBLK), 0, st, m.ne, m.n, p.N, m.tets,
+                     m.geo, Sy, m.dmask, F.rowptr.p, F.col.p, F.val.p, p);
+  hipLaunchKernelGGL(k_pc_dirichlet, dim3(nblk(m.n)), dim3(PBLK), 0, st, m.n, m.dmask, F.diag.p,
+                     F.val.p);
+  for (size_t l = 0; l + 1 < pc->lv.size(); ++l) {
+    PcLevel& A = pc->lv[l];
+    PcLevel& B = pc->lv[l + 1];
+    hipLaunchKernelGGL(k_pc_galerkin, dim3(nblk(B.nnz * PC_NFIELDS)), dim3(PBLK), 0, st, B.nnz,
+                       A.gptr.p, A.gsrc.p, A.val.p, B.val.p);
+  }
+  PcLevel& C = pc->lv.back();
+  const int64_t D = pc->dense_D;
+  if ((e = hipMemsetAsync(pc->dense.p, 0, pc->dense.bytes(), st))) return e;
+  hipLaunchKernelGGL(k_pc_dense, dim3(nblk(C.nnz * pc->nm)), dim3(PBLK), 0, st, C.n, C.rowptr.p,
+                     C.col.p, C.val.p, pc->coef, pc->dense.p);
+  if ((e = hipMemsetAsync(pc->flag.p, 0, sizeof(int), st))) return e;
+  hipLaunchKernelGGL(k_pc_invert, dim3(pc->nm), dim3(PBLK), 0, st, (int)D, pc->dense.p,
+                     pc->work.p, pc->inv.p, pc->flag.p);
+  return hipGetLastError();
+}
+
+namespace {
+
+hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
+  PcLevel& L = pc->lv[l];
+  const int nm = pc->nm;
+  if (l + 1 == pc->lv.size()) {
+    hipLaunchKernelGGL(k_pc_dense_apply, dim3(nblk(4 * L.n * nm)), dim3(PBLK), 0, st, L.n, nm,
+                       pc->inv.p, L.b.p, L.x.p);
+    return hipGetLastError();
+  }
+  const unsigned g = nblk(L.n * nm);
+  auto sweep = [&](bool from_zero) {
+    hipLaunchKernelGGL(k_pc_rows<2>, dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
+                       L.diag.p, L.val.p, pc->coef, L.b.p, from_zero ? nullptr : L.x.p, L.x2.p,
+                       pc->wj);
+    std::swap(L.x.p, L.x2.p);
+  };
+  for (int k = 0; k < pc->nu; ++k) sweep(zero_start && k == 0);
+  hipLaunchKernelGGL(k_pc_rows<1>, dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
+                     L.diag.p, L.val.p, pc->coef, L.b.p, L.x.p, L.r.p, 0.0);
+  PcLevel& C = pc->lv[l + 1];
+  hipLaunchKernelGGL(k_pc_restrict, dim3(nblk(C.n * nm * 8)), dim3(PBLK), 0, st, C.n, nm,
+                     L.mptr.p, L.mem.p, L.r.p, C.b.p);
+  hipError_t e = vcycle(pc, l + 1, true, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pc_prolong, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st, L.n, nm, L.agg.p,
+                     C.x.p, L.x.p, pc->gamma);
+  for (int k = 0; k < pc->nu; ++k) sweep(false);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename TQ, typename TZ>
+hipError_t precond_apply(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st) {
+  const int nm = pc->nm, N = pc->N;
+  PcLevel& F = pc->lv[0];
+  hipLaunchKernelGGL((k_pc_to_modes<TQ>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm, q,
+                     in_ch, pc->cs.p, F.b.p);
+  for (int c = 0; c < pc->cycles; ++c) {
+    hipError_t e = vcycle(pc, 0, c == 0, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_pc_from_modes<TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n, N, nm,
+                     F.x.p, pc->cs.p, z);
+  return hipGetLastError();
+}
+
+template <typename TQ, typename TZ>
+hipError_t precond_matvec(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st) {
+  const int nm = pc->nm, N = pc->N;
+  PcLevel& F = pc->lv[0];
+  hipLaunchKernelGGL((k_pc_to_modes<TQ>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm, q,
+                     in_ch, pc->cs.p, F.b.p);
+  hipLaunchKernelGGL(k_pc_rows<0>, dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, F.rowptr.p, F.col.p,
+                     F.diag.p, F.val.p, pc->coef, nullptr, F.b.p, F.x.p, 0.0);
+  hipLaunchKernelGGL((k_pc_from_modes<TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n, N, nm,
+                     F.x.p, pc->cs.p, z);
+  return hipGetLastError();
+}
+
+hipError_t precond_singular(Precond* pc, int* flag_host, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(flag_host, pc->flag.p, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+template hipError_t precond_apply<double, double>(Precond*, int64_t, const double*, int,
+                                                  double*, hipStream_t);
+template hipError_t precond_apply<float, double>(Precond*, int64_t, const float*, int, double*,
+                                                 hipStream_t);
+template hipError_t precond_matvec<double, double>(Precond*, int64_t, const double*, int,
+                                                   double*, hipStream_t);
+
+}  // namespace hb

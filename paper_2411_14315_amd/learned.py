@@ -19,7 +19,8 @@ from dataclasses import dataclass, replace
 
 import numpy as np
 
-from . import BC, HB_F64, Mesh, SolveOptions, _check, _ptr, _stream, load, newton_solve, residual
+from . import (BC, HB_F64, Mesh, SolveOptions, _arg, _check, _stream, load, newton_solve,
+               residual)
 
 
 class MLP:
@@ -47,23 +48,30 @@ class MLP:
 
     def forward(self, X, Y=None, stream=None):
         import torch
+        B = int(X.shape[0])
+        xp = _arg(X, "X", (B, self.widths[0]), ("float32",))
         if Y is None:
-            Y = torch.empty((X.shape[0], self.widths[-1]), dtype=torch.float32, device=X.device)
-        _check(load().hb_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(Y), _stream(stream)))
+            Y = torch.empty((B, self.widths[-1]), dtype=torch.float32, device=X.device)
+        yp = _arg(Y, "Y", (B, self.widths[-1]), ("float32",), device=X.device)
+        _check(load().hb_mlp_forward(self._h, xp, B, yp, _stream(stream)))
         return Y
 
     def loss_grad(self, X, T, grad=None, want_loss=True, stream=None):
         """Forward + backward of the mean squared error; the gradient goes to
         ``grad`` (FP32 device tensor of n_params) or the handle's own buffer."""
         loss = C.c_double()
-        _check(load().hb_mlp_loss_grad(self._h, _ptr(X), _ptr(T), X.shape[0],
-                                       None if grad is None else _ptr(grad),
+        B = int(X.shape[0])
+        xp = _arg(X, "X", (B, self.widths[0]), ("float32",))
+        tp = _arg(T, "T", (B, self.widths[-1]), ("float32",), device=X.device)
+        gp = None if grad is None else _arg(grad, "grad", (self.n_params,), ("float32",),
+                                            device=X.device)
+        _check(load().hb_mlp_loss_grad(self._h, xp, tp, B, gp,
                                        C.byref(loss) if want_loss else None, _stream(stream)))
         return float(loss.value) if want_loss else None
 
     def adam_step(self, lr: float, grad=None, stream=None):
-        _check(load().hb_mlp_adam_step(self._h, None if grad is None else _ptr(grad),
-                                       C.c_float(lr), _stream(stream)))
+        gp = None if grad is None else _arg(grad, "grad", (self.n_params,), ("float32",))
+        _check(load().hb_mlp_adam_step(self._h, gp, C.c_float(lr), _stream(stream)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -81,9 +89,21 @@ def pod_expand(mean, basis, coef, Y, base=None, stream=None):
     """Y = base + mean + basis^T coef on the device (basis rows are POD
     modes; base optional and may be Y itself)."""
     r = 0 if basis is None else int(basis.shape[0])
-    _check(load().hb_pod_expand(mean.numel(), r, None if base is None else _ptr(base),
-                                _ptr(mean), None if r == 0 else _ptr(basis),
-                                None if r == 0 else _ptr(coef), _ptr(Y), _stream(stream)))
+    L = int(mean.numel())
+    mp = _arg(mean, "mean", tuple(mean.shape))
+    yp = _arg(Y, "Y", tuple(Y.shape), device=mean.device)
+    if int(Y.numel()) != L:
+        raise ValueError(f"Y has {Y.numel()} values, mean {L}")
+    bp = None
+    if base is not None:
+        bp = _arg(base, "base", tuple(base.shape), device=mean.device)
+        if int(base.numel()) != L:
+            raise ValueError(f"base has {base.numel()} values, mean {L}")
+    Bp = cp = None
+    if r:
+        Bp = _arg(basis, "basis", (r, L), device=mean.device)
+        cp = _arg(coef, "coef", (r,), ("float32",), device=mean.device)
+    _check(load().hb_pod_expand(L, r, bp, mp, Bp, cp, yp, _stream(stream)))
     return Y
 
 

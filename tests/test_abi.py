@@ -64,3 +64,43 @@ def test_null_arguments(lib):
     assert lib.hb_residual(None, None, None, None, None, None) == hbl.HB_ERR_ARG
     assert lib.hb_jvp(None, None, None, None, None, None, 0, None) == hbl.HB_ERR_ARG
     assert lib.hb_newton_solve(None, None, None, None, None, None, None) == hbl.HB_ERR_ARG
+
+
+class _FakeMesh:
+    """Stands in for a mesh handle: the binding checks its arguments against
+    these sizes before it calls into the library."""
+    n_nodes = 10
+    n_outlets = 1
+    _h = None
+
+
+def test_binding_rejects_bad_tensors_before_launch():
+    torch = pytest.importorskip("torch")
+    m = _FakeMesh()
+    prm = hbl.Params(K=2)
+    bc = hbl.BC(torch.zeros((3, 5, 10), dtype=torch.float64), np.zeros((1, 5)), None)
+    cases = [
+        (lambda: hbl.residual(m, prm, bc, torch.zeros((4, 5, 10), dtype=torch.float32)), "dtype"),
+        (lambda: hbl.residual(m, prm, bc, torch.zeros((4, 3, 10), dtype=torch.float64)), "shape"),
+        (lambda: hbl.jvp(m, prm, bc, torch.zeros((4, 5, 9), dtype=torch.float64),
+                         torch.zeros((4, 5, 10), dtype=torch.float64)), "shape"),
+        (lambda: hbl.jvp(m, prm, bc, torch.zeros((4, 5, 10), dtype=torch.float32),
+                         torch.zeros((4, 5, 10), dtype=torch.float32)), "dtype"),
+        (lambda: hbl.newton_solve(m, hbl.Params(K=3), bc,
+                                  torch.zeros((4, 5, 10), dtype=torch.float64)), "shape"),
+        (lambda: hbl.jacobi(m, prm, bc, torch.zeros((4, 5, 10), dtype=torch.float16)), "dtype"),
+        (lambda: hbl.tm_residual(m, prm, None, torch.zeros((4, 11), dtype=torch.float64)), "shape"),
+        (lambda: hbl.precond_apply(m, prm, bc, torch.zeros((4, 5, 10), dtype=torch.float32),
+                                   torch.zeros((4, 5, 10), dtype=torch.float64)), "dtype"),
+        (lambda: hbl.residual(m, prm, bc, torch.zeros((4, 5, 10), dtype=torch.float64)),
+         "device"),
+    ]
+    for fn, what in cases:
+        with pytest.raises(hbl.HBError) as e:
+            fn()
+        assert e.value.status == hbl.HB_ERR_ARG and what in str(e.value), str(e.value)
+    # host boundary arrays are checked against the mesh and N as well
+    bad_h = hbl.BC(torch.zeros((3, 5, 10), dtype=torch.float64), np.zeros((2, 5)), None)
+    with pytest.raises(hbl.HBError) as e:
+        bad_h._c(m, 5)
+    assert "outlet_h" in str(e.value)
