@@ -181,6 +181,53 @@ def womersley_time_to_solution(hbl, torch, log, precision="fp64"):
     return res
 
 
+def periodicity(hbl, torch, log, workload="tjunction", h=3.0 / 70.0, periods=8, spp=100,
+                step_rtol=1e-6):
+    """Does the workload settle to a T-periodic flow?  The GLS time-marching
+    solver (hb_tm_march: generalized-alpha, tau-hat of eq. tauhat, each step
+    solved by Newton-GMRES with the mean-flow multigrid to step_rtol) is
+    marched period by period from the plain steady start; reported per
+    period: the relative change of the marched states against the previous
+    period at the same phases, and the outlet flow rate at the sample times.
+    A flow that settles shows the change falling period after period; a
+    flow without a T-periodic attractor keeps an O(1) change."""
+    from hbinputs.problems import c1_womersley, c2_tjunction
+    P = c2_tjunction(K=10, h=h) if workload == "tjunction" else c1_womersley()
+    prm = P.params
+    n, T = P.mesh.n_nodes, prm.period
+    gm = hbl.Mesh.from_mesh(P.mesh)
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")  # noqa: E731
+    bc = hbl.BC(to(P.dirichlet), P.outlet_h, P.outlet_R)
+    bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
+    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
+    from dataclasses import replace
+    hbl.newton_solve(gm, replace(prm, K=0), bc0, Ys,
+                     hbl.SolveOptions(rtol=1e-8, max_newton=60, max_gmres=500,
+                                      precond=hbl.HB_PREC_MEANFLOW), raise_on_noconv=False)
+    Y = Ys[:, 0].contiguous().clone()
+    A = torch.zeros((3, n), dtype=torch.float64, device="cuda:0")
+    traj = torch.empty((spp, 4, n), dtype=torch.float64, device="cuda:0")
+    prev = None
+    rows = []
+    for k in range(periods):
+        opts = hbl.TmOptions(t0=k * T, dt=T / spp, n_steps=spp, rtol=step_rtol, gmres_eta=0.03,
+                             max_newton=15, max_gmres=500, precond=hbl.HB_PREC_MEANFLOW)
+        t = time.time()
+        r = hbl.tm_march(gm, prm, bc, Y, A, opts, traj=traj, raise_on_noconv=False)
+        vel = traj[:, :3]
+        row = {"period": k + 1, "wall_s": time.time() - t, "newton_iters": r["newton_iters"],
+               "gmres_iters": r["gmres_iters"], "status": r["status"],
+               "max_step_residual": r["max_step_residual"],
+               "velocity_change": None if prev is None else
+               float(torch.linalg.norm(vel - prev) / torch.linalg.norm(vel))}
+        rows.append(row)
+        log(f"periodicity {workload} period {k + 1}: {row}")
+        prev = vel.clone()
+    gm.close()
+    return {"workload": workload, "n_nodes": n, "steps_per_period": spp, "step_rtol": step_rtol,
+            "periods": rows}
+
+
 def tm_vs_hb(hbl, torch, log, periods, spp):
     """The paper's comparison on the Womersley-pipe workload: the GLS
     time-marching solver (hb_tm_march, dt = T/spp, per-step Newton to three
@@ -427,6 +474,9 @@ def main():
     ap.add_argument("--learned-test", type=int, default=12)
     ap.add_argument("--cfl-study", choices=["tjunction", "womersley"], default=None,
                     help="fixed-pseudo-step CFL study on this workload (skips the main bench)")
+    ap.add_argument("--periodicity", choices=["tjunction", "womersley"], default=None,
+                    help="march the workload period by period with the time-marching solver "
+                         "and report the cycle-to-cycle change (skips the main bench)")
     ap.add_argument("--tm-periods", type=int, default=6,
                     help="periods of the time-marching comparison on the Womersley pipe (0: off)")
     ap.add_argument("--tm-spp", type=int, default=50, help="time-marching steps per period")
@@ -446,6 +496,11 @@ def main():
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
+    if args.periodicity:
+        print(json.dumps({"periodicity": periodicity(hbl, torch, log, args.periodicity,
+                                                     h=args.h, periods=args.tm_periods)}),
+              flush=True)
+        return
     if args.cfl_study:
         print(json.dumps({"cfl_study": cfl_study(hbl, torch, log, args.cfl_study)}), flush=True)
         return

@@ -189,6 +189,9 @@ typedef struct {
                          starting state (mass-weighted velocity norms);
                          >= 0: held at this value                           */
   int32_t verbose;    /* 1: one line per step on stderr                     */
+  int32_t precond;    /* HB_PREC_JACOBI (0) or HB_PREC_MEANFLOW (the same
+                         multigrid as hb_newton_solve's, K = 0, with the
+                         step's 1.5 rho/dt mass term)                        */
 } hb_tm_opts;
 
 typedef struct {
@@ -202,7 +205,8 @@ typedef struct {
  * prm->period give the harmonics) and modal outlet traction (host).  Each
  * step is solved by Newton-GMRES with the exact step Jacobian, right-
  * preconditioned by the Jacobi diagonal of the paper's tangent plus
- * 1.5 rho/dt times the mass diagonal.  Y (device [4][n]) and A (device
+ * 1.5 rho/dt times the mass diagonal, or by the multigrid of
+ * HB_PREC_MEANFLOW (opts->precond).  Y (device [4][n]) and A (device
  * [3][n]) hold the state and acceleration at t0 on entry and at the last
  * step on return; traj (device [n_steps][4][n], or NULL) receives the
  * state after every step.  Synchronous on return.  HB_ERR_NOCONV if a step
@@ -266,7 +270,7 @@ typedef struct {
                           previous one (or is not finite) is damped by 1/2,
                           1/4, ... 1/64 until the residual falls below the
                           previous one; the trial with the smallest residual
-                          is kept; 0: 3.0; < 0: take every full step          */
+                          is kept; 0: 100; < 0: take every full step          */
   double dt_growth;   /* after an accepted step the pseudo step is scaled by the
                          residual ratio, and by at least dt_growth when the
                          residual did not grow (0: 1, plain switched evolution
@@ -288,6 +292,10 @@ typedef struct {
   double jv_ms;    /* total time spent in Krylov operator applications */
   int32_t n_jv;
   int32_t rejected; /* Newton steps taken damped (alpha < 1)          */
+  double mass_defect; /* at the returned state: max over samples of
+                         |sum_A r^c_A(t_n)| (the net boundary outflow, since
+                         sum_A N_A = 1) over max over samples of the total
+                         outlet flow |sum_k Q_k(t_n)|                     */
 } hb_solve_report;
 
 /* Inexact Newton with pseudo-time continuation (Section 2.3): the tangent
@@ -332,6 +340,16 @@ typedef struct {
 int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
                      double shift, const hb_precond_opts* opts, int32_t op, const double* X,
                      double* OUT, void* stream);
+/* Outlet flow rates and mass balance at Y (device [4][N][n]; Dirichlet entries
+ * from bc): Q (host [n_outlets][N]) = int_{outlet k} u(t_n) . n, the flux
+ * through each outlet group at each sample time (exact for P1 fields); defect
+ * (host [N], or NULL) = sum over all nodes of the continuity rows of eq. Rmc
+ * at each sample, which equals the net outflow through the whole boundary
+ * (sum_A N_A = 1, so the stabilisation part cancels): Q_out - Q_in.  For a
+ * converged solution it vanishes with the residual.  Waits for the stream. */
+int hb_outlet_flow(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+                   double* Q, double* defect, void* stream);
+
 /* Node counts of the preconditioner's levels (finest first): sizes[0..max-1];
  * *n_levels = number of levels (0 before the hierarchy is built). */
 int hb_precond_levels(const hb_mesh* mesh, int64_t* sizes, int32_t max, int32_t* n_levels);

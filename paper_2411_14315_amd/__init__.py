@@ -50,7 +50,7 @@ class _TmOpts(C.Structure):
     _fields_ = [("t0", C.c_double), ("dt", C.c_double), ("n_steps", C.c_int32),
                 ("rtol", C.c_double), ("atol", C.c_double), ("gmres_eta", C.c_double),
                 ("restart", C.c_int32), ("max_newton", C.c_int32), ("max_gmres", C.c_int32),
-                ("omega_hat", C.c_double), ("verbose", C.c_int32)]
+                ("omega_hat", C.c_double), ("verbose", C.c_int32), ("precond", C.c_int32)]
 
 
 class _TmReport(C.Structure):
@@ -79,7 +79,7 @@ class _Report(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("status", C.c_int32),
                 ("r0", C.c_double), ("r_final", C.c_double), ("r_ref", C.c_double),
                 ("wall_s", C.c_double), ("jv_ms", C.c_double), ("n_jv", C.c_int32),
-                ("rejected", C.c_int32)]
+                ("rejected", C.c_int32), ("mass_defect", C.c_double)]
 
 
 _lib = None
@@ -121,12 +121,14 @@ def load():
     lib.hb_precond_apply.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, dbl,
                                      C.POINTER(_PcOpts), i32, vp, vp, vp]
     lib.hb_precond_levels.argtypes = [vp, vp, i32, C.POINTER(i32)]
+    lib.hb_outlet_flow.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, vp, vp, vp]
     lib.hb_last_error.restype = C.c_char_p
     for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
                  "hb_newton_solve", "hb_set_timing", "hb_last_timings", "hb_mlp_create",
-                 "hb_mlp_num_params", "hb_mlp_get_params", "hb_mlp_forward", "hb_mlp_loss_grad",
+                 "hb_mlp_num_params", "hb_mlp_get_params", "hb_mlp_forward",
+                 "hb_mlp_loss_grad",
                  "hb_mlp_adam_step", "hb_pod_expand", "hb_tm_residual", "hb_tm_jvp",
-                 "hb_tm_march", "hb_precond_apply", "hb_precond_levels"):
+                 "hb_tm_march", "hb_precond_apply", "hb_precond_levels", "hb_outlet_flow"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -369,11 +371,12 @@ class TmOptions:
     max_gmres: int = 1000
     omega_hat: float = -1.0  # < 0: eq. tauhat from each step's starting state
     verbose: int = 0
+    precond: int = HB_PREC_JACOBI
 
     def _c(self):
         return _TmOpts(self.t0, self.dt, self.n_steps, self.rtol, self.atol, self.gmres_eta,
                        self.restart, self.max_newton, self.max_gmres, self.omega_hat,
-                       self.verbose)
+                       self.verbose, self.precond)
 
 
 def tm_march(mesh: Mesh, params, bc: BC, Y, A, opts: TmOptions, traj=None, stream=None,
@@ -428,7 +431,7 @@ class SolveOptions:
     amg_sweeps: int = 0   # HB_PREC_MEANFLOW: Jacobi sweeps per level (0: 2)
     amg_cycles: int = 0   # HB_PREC_MEANFLOW: V-cycles per application (0: 1)
     amg_weight: float = 0.0  # HB_PREC_MEANFLOW: Jacobi damping (0: 0.7)
-    reject_ratio: float = 0.0  # undo steps whose residual grows beyond this ratio (0: 2; <0: never)
+    reject_ratio: float = 0.0  # damp steps whose residual grows beyond this ratio (0: 100; <0: never)
     dt_growth: float = 0.0     # least pseudo-step growth after a non-increasing step (0: 1)
     amg_aggregation: int = 0   # HB_PREC_MEANFLOW: 0 pairwise matching twice, 1 node + neighbours
     amg_coarse_weight: float = 0.0  # HB_PREC_MEANFLOW: coarse-correction weight (0: 0.7)
@@ -488,3 +491,17 @@ def precond_levels(mesh: Mesh) -> list:
     nl = C.c_int32()
     _check(load().hb_precond_levels(mesh._h, sizes.ctypes.data, 32, C.byref(nl)))
     return [int(x) for x in sizes[:nl.value]]
+
+
+def outlet_flow(mesh: Mesh, params, bc: BC, Y, stream=None):
+    """Outlet flow rates Q (n_outlets, N) at the sample times and the mass
+    balance defect (N,) = net boundary outflow per sample (the continuity
+    rows summed over all nodes); see hb_outlet_flow."""
+    p = _params(params)
+    yp = _arg(Y, "Y", _modal_shape(mesh, p))
+    Q = np.zeros((mesh.n_outlets, p.N))
+    d = np.zeros(p.N)
+    pc, bcc = p._c(), bc._c(mesh, p.N)
+    _check(load().hb_outlet_flow(mesh._h, C.byref(pc), C.byref(bcc), yp, Q.ctypes.data,
+                                 d.ctypes.data, _stream(stream)))
+    return Q, d

@@ -886,6 +886,40 @@ int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc,
   return HB_OK;
 }
 
+int hb_outlet_flow(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
+                   double* Q, double* defect, void* stream) {
+  if (!mesh || !Y || !Q) return fail(HB_ERR_ARG, "NULL argument");
+  hb_mesh* m = const_cast<hb_mesh*>(mesh);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = prepare(m, prm, bc, st);
+  if (rc) return rc;
+  Workspace& w = m->ws;
+  const int N = w.N;
+  const int nout = m->dm.n_out;
+  Ptrs s = small_ptrs(m);
+  const double* tab = w.tab.as<double>();
+  // Q (zeroed by the transform) holds the flux of every outlet at every sample
+  HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab,
+                                                w.Sy.as<double>(), w.acc.as<double>(), s.Q,
+                                                nout * N, st));
+  HB_CHECK(hb::outlet_flux<double>(m->dm, N, w.Sy.as<double>(), s.Q, st));
+  std::vector<double> qh((size_t)nout * N);
+  HB_CHECK(hipMemcpyAsync(qh.data(), s.Q, sizeof(double) * qh.size(), hipMemcpyDeviceToHost, st));
+  if (defect) {
+    // continuity rows of eq. Rmc summed over all nodes, per sample
+    const Phys p = make_phys(prm, 0.0);
+    HB_CHECK(hb::elem_residual(m->dm, p, w.Sy.as<double>(), w.acc.as<double>(),
+                               pick_blocks(m, N), st));
+    HB_CHECK(m->sb.uc.ensure(sizeof(double) * N));
+    double* sums = m->sb.uc.as<double>();
+    HB_CHECK(hb::channel_sum(w.acc.as<double>(), m->dm.n, hb::NCH, N, 3, sums, st));
+    HB_CHECK(hipMemcpyAsync(defect, sums, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+  }
+  HB_CHECK(hipStreamSynchronize(st));
+  std::memcpy(Q, qh.data(), sizeof(double) * qh.size());
+  return HB_OK;
+}
+
 int hb_precond_levels(const hb_mesh* mesh, int64_t* sizes, int32_t max, int32_t* n_levels) {
   if (!mesh || !n_levels || (max > 0 && !sizes)) return fail(HB_ERR_ARG, "NULL argument");
   *n_levels = hb::precond_levels(mesh->pc, sizes, max);
@@ -1412,14 +1446,15 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   // relaxation from max(reference, initial residual), so a start whose
   // residual is already below the reference takes a larger step at once;
   // later steps scale dt by the residual ratio of the accepted step (at
-  // least by dt_growth when the residual did not grow).  Globalisation: a
-  // step whose residual exceeds reject_ratio times the previous one (or is
-  // not finite) is damped, y + alpha delta with alpha = 1/2, 1/4, ... 1/64,
-  // until the residual falls below the previous one, and the trial with the
-  // smallest residual is kept (a smaller pseudo step would not help here:
-  // the pseudo-time term does not reach the pressure update); the next
+  // least by dt_growth when the residual did not grow).  A pseudo-time step
+  // is not a descent step (the mass shift holds the velocity back while the
+  // pressure follows the continuity rows at once), so ordinary growth of the
+  // residual is accepted; only a step whose residual exceeds reject_ratio
+  // times the previous one (or is not finite) is damped, y + alpha delta
+  // with alpha = 1/2, 1/4, ... 1/64, until the residual falls below the
+  // previous one, keeping the trial with the smallest residual; the next
   // pseudo step is scaled by sqrt(alpha), never below 1/100 of the first.
-  const double reject = opts->reject_ratio == 0 ? 3.0 : opts->reject_ratio;
+  const double reject = opts->reject_ratio == 0 ? 100.0 : opts->reject_ratio;
   const double grow_min = opts->dt_growth > 0 ? opts->dt_growth : 1.0;
   constexpr int kMaxHalve = 6;
   double dt = std::min(dt0 * ser_ref / std::max(rn, 1e-300), dt_max);
@@ -1511,6 +1546,30 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   }
   report->newton_iters = it;
   report->r_final = rn;
+  {
+    // mass balance at the final state: the continuity rows summed over all
+    // nodes equal the net boundary outflow (sum_A N_A = 1), relative to the
+    // largest total outlet flow over the samples
+    Ptrs s = small_ptrs(m);
+    const int nout = m->dm.n_out;
+    HB_CHECK(hb::vec_zero<double>(s.Q, (int64_t)nout * N, st));
+    HB_CHECK(hb::outlet_flux<double>(m->dm, N, w.Sy.as<double>(), s.Q, st));
+    HB_CHECK(m->sb.uc.ensure(sizeof(double) * N));
+    HB_CHECK(hb::channel_sum(r, m->dm.n, 4, N, 3, m->sb.uc.as<double>(), st));
+    std::vector<double> qh((size_t)nout * N), dh(N);
+    HB_CHECK(hipMemcpyAsync(qh.data(), s.Q, sizeof(double) * qh.size(), hipMemcpyDeviceToHost,
+                            st));
+    HB_CHECK(hipMemcpyAsync(dh.data(), m->sb.uc.p, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HB_CHECK(hipStreamSynchronize(st));
+    double qmax = 0.0, dmax = 0.0;
+    for (int k = 0; k < N; ++k) {
+      double q = 0.0;
+      for (int o = 0; o < nout; ++o) q += qh[(size_t)o * N + k];
+      qmax = std::max(qmax, std::fabs(q));
+      dmax = std::max(dmax, std::fabs(dh[k]));
+    }
+    report->mass_defect = qmax > 0 ? dmax / qmax : dmax;
+  }
   HB_CHECK(hb::samples_to_modal<double, double>(m->dm, N, w.Sy.as<double>(), 0, 0, hb::NCH, tab,
                                                 Y, st));
   HB_CHECK(hipStreamSynchronize(st));
@@ -1587,6 +1646,11 @@ int tm_march_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y, d
       rc = S.alloc();
       if (rc) return rc;
       HB_CHECK(m->sb.rbuf.ensure(sizeof(double) * S.L));
+      if (o->precond == HB_PREC_MEANFLOW) {
+        rc = ensure_precond(m, kCoarseMax, 1, 1);
+        if (rc) return rc;
+        S.use_pc = true;
+      }
       allocated = true;
     }
     S.tau_add = pp.tau_add;
@@ -1608,9 +1672,15 @@ int tm_march_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y, d
     while (rn > target && it < o->max_newton) {
       Phys pj = make_phys(&p0, prm->rho * kTmC1 / dt);
       pj.tau_add = pp.tau_add;
-      HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), n * 2, st));
-      HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), 0, st));
-      HB_CHECK(hb::jacobi_out(m->dm, 1, 2, w.dg.as<double>(), nullptr, w.dinv.as<double>(), st));
+      if (S.use_pc) {
+        HB_CHECK(hb::precond_setup(m->pc, m->dm, pj, w.Sy.as<double>(), pj.shift, 2, 1, 0.7, 0.7,
+                                   st));
+      } else {
+        HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), n * 2, st));
+        HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), 0, st));
+        HB_CHECK(hb::jacobi_out(m->dm, 1, 2, w.dg.as<double>(), nullptr, w.dinv.as<double>(),
+                                st));
+      }
       int gi = 0;
       rc = S.gmres(r, 0.0, o->gmres_eta, o->max_gmres, gi);
       if (rc) return rc;
@@ -1664,6 +1734,8 @@ int hb_tm_march(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, doub
   if (opts->restart < 1 || opts->restart > 512) return fail(HB_ERR_ARG, "restart must be 1..512");
   if (opts->max_newton < 0 || opts->max_gmres < 1) return fail(HB_ERR_ARG, "bad iteration limits");
   if (std::isnan(opts->omega_hat)) return fail(HB_ERR_ARG, "omega_hat is NaN");
+  if (opts->precond != HB_PREC_JACOBI && opts->precond != HB_PREC_MEANFLOW)
+    return fail(HB_ERR_ARG, "precond must be HB_PREC_JACOBI or HB_PREC_MEANFLOW");
   return tm_march_run(const_cast<hb_mesh*>(mesh), prm, bc, Y, A, traj, opts, report,
                       (hipStream_t)stream, t0);
 }

@@ -173,6 +173,9 @@ template <typename TU>
 hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const uint8_t* dmask,
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st);
 hipError_t vec_nonfinite(const double* x, int64_t L, int* flag, hipStream_t st);
+// out[s] = sum over nodes a of X[a][ch][s] (X [n][nch][N]); out [N] device
+hipError_t channel_sum(const double* X, int64_t n, int nch, int N, int ch, double* out,
+                       hipStream_t st);
 // y = a + alpha (b - a); y may alias a or b
 hipError_t vec_blend(double* y, const double* a, const double* b, int64_t L, double alpha,
                      hipStream_t st);

@@ -1048,12 +1048,14 @@ k_elem_jacobi(DevMesh m, Phys p, const double* __restrict__ Sy, double* __restri
 // workgroup per sample, per-outlet partial sums in LDS.
 template <typename R>
 __global__ void __launch_bounds__(BLK)
-k_outlet_flux(DevMesh m, int N, const R* __restrict__ S, double* __restrict__ Q) {
+k_outlet_flux(DevMesh m, int N, const R* __restrict__ S, double* __restrict__ Q, int64_t chunk) {
   __shared__ double sq[64];
   const int s = blockIdx.x;
+  const int64_t f0 = (int64_t)blockIdx.y * chunk;
+  const int64_t f1 = min<int64_t>(m.nof, f0 + chunk);
   for (int k = threadIdx.x; k < m.n_out; k += BLK) sq[k] = 0.0;
   __syncthreads();
-  for (int64_t f = threadIdx.x; f < m.nof; f += BLK) {
+  for (int64_t f = f0 + threadIdx.x; f < f1; f += BLK) {
     double ub[3] = {0, 0, 0};
 #pragma unroll
     for (int A = 0; A < 3; ++A) {
@@ -1067,7 +1069,7 @@ k_outlet_flux(DevMesh m, int N, const R* __restrict__ S, double* __restrict__ Q)
     atomicAdd(&sq[m.oid[f]], v);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < m.n_out; k += BLK) Q[k * N + s] = sq[k];
+  for (int k = threadIdx.x; k < m.n_out; k += BLK) atomicAdd(&Q[k * N + s], sq[k]);
 }
 
 // Outlet rows: -int N_A h n_i with h = hs - R Q, and the backflow term
@@ -1393,6 +1395,26 @@ k_copy_scaled(TD* __restrict__ d, const TS* __restrict__ x, int64_t L, double s)
     d[i] = (TD)(s * (double)x[i]);
 }
 
+// out[s] += sum over nodes of X[a][ch][s] (X has nch channels of N samples);
+// one workgroup per (sample, chunk of nodes)
+__global__ void __launch_bounds__(BLK)
+k_channel_sum(const double* __restrict__ X, int64_t n, int nch, int N, int ch, int64_t chunk,
+              double* __restrict__ out) {
+  __shared__ double red[BLK];
+  const int s = blockIdx.x;
+  const int64_t a0 = (int64_t)blockIdx.y * chunk;
+  const int64_t a1 = min<int64_t>(n, a0 + chunk);
+  double v = 0.0;
+  for (int64_t a = a0 + threadIdx.x; a < a1; a += BLK) v += X[(a * nch + ch) * N + s];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = BLK / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(&out[s], red[0]);
+}
+
 // y = a + alpha (b - a) (damped Newton step between two states)
 __global__ void __launch_bounds__(BLK)
 k_blend(double* __restrict__ y, const double* __restrict__ a, const double* __restrict__ b,
@@ -1502,7 +1524,12 @@ hipError_t finish_rows(const DevMesh& m, int N, const TA* acc, int use_z, const 
 template <typename R>
 hipError_t outlet_flux(const DevMesh& m, int N, const R* S, double* Q, hipStream_t st) {
   if (m.nof == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_outlet_flux<R>), dim3(N), dim3(BLK), 0, st, m, N, S, Q);
+  // Q must be zero on entry (the transform that fills S zeroes it): each
+  // workgroup adds the flux of one chunk of outlet faces at one sample
+  constexpr int64_t kChunk = 2048;
+  const int64_t nch = (m.nof + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL((k_outlet_flux<R>), dim3(N, (unsigned)nch), dim3(BLK), 0, st, m, N, S, Q,
+                     kChunk);
   return hipGetLastError();
 }
 
@@ -1649,6 +1676,17 @@ hipError_t vec_mul_dinv_add(double* y, const TU* u, const double* dinv, const ui
                             int64_t n, int N, int nch_y, int nch_u, double s, hipStream_t st) {
   hipLaunchKernelGGL((k_mul_dinv_add<TU>), dim3(blocks_for(n * 4 * N)), dim3(BLK), 0, st, y, u,
                      dinv, dmask, n, N, nch_y, nch_u, s);
+  return hipGetLastError();
+}
+
+hipError_t channel_sum(const double* X, int64_t n, int nch, int N, int ch, double* out,
+                       hipStream_t st) {
+  hipError_t e = vec_zero<double>(out, N, st);
+  if (e != hipSuccess || n == 0) return e;
+  constexpr int64_t kChunk = 16384;
+  const int64_t nch_ = (n + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(k_channel_sum, dim3(N, (unsigned)nch_), dim3(BLK), 0, st, X, n, nch, N, ch,
+                     kChunk, out);
   return hipGetLastError();
 }
 

@@ -141,3 +141,35 @@ def test_precond_argument_errors(tiny):
     with pytest.raises(hbl.HBError) as e:
         hbl.precond_apply(c.gm, c.P.params, c.bc, Y, Y.float())
     assert e.value.status == hbl.HB_ERR_ARG
+
+
+@pytest.mark.parametrize("case", ["c1", "tj"])
+def test_outlet_flow_and_mass_defect(case, request):
+    """hb_outlet_flow against the oracle's outlet flux and its continuity rows
+    summed over all nodes (the identity sum_A r^c_A = net boundary outflow is
+    pinned on the oracle side)."""
+    from oracle import residual as ores
+    c = request.getfixturevalue(case)
+    prm = c.P.params
+    Y = seeded_state(c.P, 40)
+    Q, d = hbl.outlet_flow(c.gm, prm, c.bc, dev(Y))
+    y = api.samples_of(c.om, prm, Y, c.P.dirichlet)
+    Qr = ores.outlet_flux(c.om, y[:3])
+    assert rel(Q, Qr) <= 1e-12
+    r = ores.residual_samples(c.om, prm, y, api.h_samples(prm, c.P.outlet_h), c.P.outlet_R,
+                              api.H_of(prm))
+    dr = r[3].sum(axis=1)
+    assert np.max(np.abs(d - dr)) <= 1e-10 * np.max(np.abs(r[3]).sum(axis=1))
+
+
+def test_solve_reports_mass_balance(c1):
+    g = np.load(os.path.join(HERE, "golden", "c1_solution.npz"))
+    Y = dev(g["Y0"])
+    rep0 = hbl.newton_solve(c1.gm, c1.P.params, c1.bc, Y.clone(), hbl.SolveOptions(max_newton=0),
+                            raise_on_noconv=False)
+    rep = hbl.newton_solve(c1.gm, c1.P.params, c1.bc, Y,
+                           hbl.SolveOptions(rtol=1e-12, max_newton=100,
+                                            precond=hbl.HB_PREC_MEANFLOW))
+    print("mass defect: plain start", rep0["mass_defect"], "solution", rep["mass_defect"],
+          flush=True)
+    assert rep["status"] == 0 and rep["mass_defect"] <= 1e-9 < rep0["mass_defect"]
