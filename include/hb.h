@@ -391,6 +391,16 @@ int hb_mlp_num_params(const hb_mlp* net, int64_t* count);
 int hb_mlp_get_params(const hb_mlp* net, float* host_out);
 /* Y (device [B][out]) = net(X) (device [B][in]). */
 int hb_mlp_forward(hb_mlp* net, const float* X, int32_t B, float* Y, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward pass as hb_mlp_forward, Y (device [B][out]) = net(X) (device
+ * [B][in]), with the hidden activations in a fixed library-owned device array
+ * of 16 MiB per GPU (held until the process ends) instead of the handle's
+ * buffers.  Requires B * (largest hidden or output width) <= 1,048,576, else
+ * HB_ERR_ARG.  Calls no allocating routine.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU race (order them on one stream).
+ * Asynchronous on the stream. */
+int hb_mlp_forward_noalloc(const hb_mlp* net, const float* X, int32_t B, float* Y, void* stream);
 /* Mean squared error against T (device [B][out]) and its gradient with
  * respect to the parameters: grad device [n_params] (NULL = internal
  * buffer used by hb_mlp_adam_step); *loss (host, may be NULL) waits for the

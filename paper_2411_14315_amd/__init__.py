@@ -115,6 +115,7 @@ def load():
     lib.hb_mlp_num_params.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.hb_mlp_get_params.argtypes = [vp, vp]
     lib.hb_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+    lib.hb_mlp_forward_noalloc.argtypes = [vp, vp, i32, vp, vp]
     lib.hb_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, C.POINTER(C.c_double), vp]
     lib.hb_mlp_adam_step.argtypes = [vp, vp, C.c_float, vp]
     lib.hb_pod_expand.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp]
@@ -126,7 +127,7 @@ def load():
     for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
                  "hb_newton_solve", "hb_set_timing", "hb_last_timings", "hb_mlp_create",
                  "hb_mlp_num_params", "hb_mlp_get_params", "hb_mlp_forward",
-                 "hb_mlp_loss_grad",
+                 "hb_mlp_forward_noalloc", "hb_mlp_loss_grad",
                  "hb_mlp_adam_step", "hb_pod_expand", "hb_tm_residual", "hb_tm_jvp",
                  "hb_tm_march", "hb_precond_apply", "hb_precond_levels", "hb_outlet_flow"):
         getattr(lib, name).restype = C.c_int

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -150,6 +151,32 @@ k_pod_expand(int64_t L, int r, const double* base, const double* __restrict__ me
 }
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + BLK - 1) / BLK); }
+
+// Device-resident activation storage of hb_mlp_forward_noalloc: one copy per
+// GPU, held until the process ends.  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress (per device).
+constexpr int64_t kScratchFloats = int64_t(4) << 20;  // 16 MiB
+__device__ __align__(256) float scratch[kScratchFloats];
+constexpr int kMaxDevices = 64;
+float* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The address of this device's `scratch` (looked up once per device).
+hipError_t scratch_ptr(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 struct Buf {
   void* p = nullptr;
@@ -305,6 +332,35 @@ int hb_mlp_forward(hb_mlp* n, const float* X, int32_t B, float* Y, void* stream)
   const int L = n->layers();
   HB_MCHECK(hipMemcpyAsync(Y, n->act.as<float>() + n->aoff[L],
                            sizeof(float) * (size_t)B * n->widths[L], hipMemcpyDeviceToDevice, st));
+  return HB_OK;
+}
+
+int hb_mlp_forward_noalloc(const hb_mlp* n, const float* X, int32_t B, float* Y, void* stream) {
+  if (!n || !X || !Y || B < 1) return mfail(HB_ERR_ARG, "bad argument");
+  int maxw = 0;
+  for (int l = 1; l < n->layers(); ++l) maxw = n->widths[l] > maxw ? n->widths[l] : maxw;
+  maxw = n->widths.back() > maxw ? n->widths.back() : maxw;
+  // [Z | A] for two hidden layers in turn; the last layer writes A into Y
+  if ((int64_t)B * maxw * 4 > kScratchFloats)
+    return mfail(HB_ERR_ARG, "batch too large for the device scratch: B * max width must be <= " +
+                                 std::to_string(kScratchFloats / 4));
+  float* sc = nullptr;
+  HB_MCHECK(scratch_ptr(&sc));
+  hipStream_t st = (hipStream_t)stream;
+  const uint16_t* w16 = n->w16.as<uint16_t>();
+  const int64_t region = (int64_t)B * maxw;
+  const float* in = X;
+  for (int l = 1; l <= n->layers(); ++l) {
+    const int ni = n->widths[l - 1], no = n->widths[l];
+    const bool last = l == n->layers();
+    float* Z = sc + (int64_t)((l - 1) & 1) * 2 * region;
+    float* A = last ? Y : Z + region;
+    hipLaunchKernelGGL(k_dense_fwd, dim3(nblocks((int64_t)B * no)), dim3(BLK), 0, st, in,
+                       w16 + n->woff[l - 1], w16 + n->boff[l - 1], B, ni, no, last ? 0 : 1, Z,
+                       A);
+    HB_MCHECK(hipGetLastError());
+    in = A;
+  }
   return HB_OK;
 }
 

@@ -56,6 +56,15 @@ class MLP:
         _check(load().hb_mlp_forward(self._h, xp, B, yp, _stream(stream)))
         return Y
 
+    def forward_noalloc(self, X, Y, stream=None):
+        """The same forward pass with the hidden activations in the library's
+        fixed device array (no allocation; Y must be given)."""
+        B = int(X.shape[0])
+        xp = _arg(X, "X", (B, self.widths[0]), ("float32",))
+        yp = _arg(Y, "Y", (B, self.widths[-1]), ("float32",), device=X.device)
+        _check(load().hb_mlp_forward_noalloc(self._h, xp, B, yp, _stream(stream)))
+        return Y
+
     def loss_grad(self, X, T, grad=None, want_loss=True, stream=None):
         """Forward + backward of the mean squared error; the gradient goes to
         ``grad`` (FP32 device tensor of n_params) or the handle's own buffer."""
