@@ -178,3 +178,152 @@ def march_bdf2(blocks, mu, rho, dir_mask, g_of_t, h_of_t, load, x0, x1, dt, n_st
         xm, xc = xc, xn
         out.append(xn.reshape(4, n))
     return out
+
+
+# ------------------------------------------- independent steady GLS solver
+
+
+_QA4 = (5.0 + 3.0 * np.sqrt(5.0)) / 20.0
+_QB4 = (5.0 - np.sqrt(5.0)) / 20.0
+
+
+def _tet_grads(xyz, tets):
+    """Gradients of the P1 basis from face normals: grad N_A = -n_A |f_A| /
+    (3 V), n_A the outward unit normal of the face opposite node A; and the
+    volume V.  Written from the cross-product identity, not from J^-1."""
+    X = xyz[tets]                                        # (E, 4, 3)
+    V = np.einsum("ei,ei->e", X[:, 1] - X[:, 0],
+                  np.cross(X[:, 2] - X[:, 0], X[:, 3] - X[:, 0])) / 6.0
+    if np.any(V <= 0):
+        raise ValueError("tetrahedra must be positively oriented")
+    G = np.empty((tets.shape[0], 4, 3))
+    for A in range(4):
+        o = [k for k in range(4) if k != A]
+        a, b, c = X[:, o[0]], X[:, o[1]], X[:, o[2]]
+        nA = np.cross(b - a, c - a)                      # |nA| = 2 |f_A|
+        nA *= np.sign(np.einsum("ei,ei->e", nA, a - X[:, A]))[:, None]   # outward from A
+        G[:, A] = -nA / (6.0 * V[:, None])
+    return G, V
+
+
+def steady_gls_residual(xyz, tets, u, p, mu, rho, C_I, ofaces, onormal, oarea, h_out, beta):
+    """Steady GLS Navier-Stokes residual (Section 2.2/2.3 with H = 0):
+    momentum rows int N_A rho u.grad u_i + mu grad N_A . grad u_i - d_i N_A p
+    + (u.grad N_A) tau (rho u.grad u_i + d_i p), outlet -int N_A h n_i and
+    backflow -int N_A rho beta/2 min(u.n, 0) u_i; continuity rows
+    int N_A div u + (1/rho) d_i N_A tau (rho u.grad u_i + d_i p); tau from the
+    4-point rule with xi = sum_k grad N_k grad N_k^T (k = 1..3).
+    u (n, 3), p (n,); returns (rm (n, 3), rc (n,))."""
+    nu = mu / rho
+    G, V = _tet_grads(xyz, tets)
+    xi = np.einsum("eki,ekj->eij", G[:, 1:], G[:, 1:])
+    xx = np.einsum("eij,eij->e", xi, xi)
+    ue = u[tets]                                         # (E, 4, 3)
+    pe = p[tets]                                         # (E, 4)
+    gu = np.einsum("eai,eaj->eij", ue, G)                # d_j u_i
+    gp = np.einsum("ea,eaj->ej", pe, G)
+    div = np.einsum("eii->e", gu)
+    rm = np.zeros((xyz.shape[0], 3))
+    rc = np.zeros(xyz.shape[0])
+    lm = np.zeros((tets.shape[0], 4, 3))
+    lc = np.zeros((tets.shape[0], 4))
+    for q in range(4):
+        w = np.full(4, _QB4)
+        w[q] = _QA4
+        uq = np.einsum("a,eai->ei", w, ue)
+        pq = np.einsum("a,ea->e", w, pe)
+        conv = np.einsum("ej,eij->ei", uq, gu)
+        tau = 1.0 / np.sqrt(np.einsum("ei,eij,ej->e", uq, xi, uq) + C_I * nu * nu * xx)
+        Ls = rho * conv + gp                             # strong residual (viscous part 0)
+        ugN = np.einsum("ei,eai->ea", uq, G)
+        wq = V / 4.0
+        lm += wq[:, None, None] * (w[None, :, None] * rho * conv[:, None, :]
+                                   - G * pq[:, None, None]
+                                   + ugN[:, :, None] * tau[:, None, None] * Ls[:, None, :])
+        lc += wq[:, None] * (w[None, :] * div[:, None]
+                             + np.einsum("eai,ei->ea", G, tau[:, None] * Ls) / rho)
+    lm += mu * V[:, None, None] * np.einsum("eaj,eij->eai", G, gu)
+    for A in range(4):
+        np.add.at(rm, tets[:, A], lm[:, A])
+        np.add.at(rc, tets[:, A], lc[:, A])
+    # outlet: traction and backflow on the 3-point rule
+    uf = u[ofaces]                                       # (F, 3, 3)
+    for q in range(3):
+        w = np.full(3, 1.0 / 6.0)
+        w[q] = 2.0 / 3.0
+        uq = np.einsum("a,fai->fi", w, uf)
+        un = np.einsum("fi,fi->f", uq, onormal)
+        t = -(h_out * onormal + 0.5 * rho * beta * np.minimum(un, 0.0)[:, None] * uq)
+        for A in range(3):
+            np.add.at(rm, ofaces[:, A], (oarea / 3.0)[:, None] * w[A] * t)
+    return rm, rc
+
+
+def steady_gls_solve(xyz, tets, mu, rho, C_I, dir_mask, g, ofaces, onormal, oarea, h_out, beta,
+                     tol=1e-12, max_it=30):
+    """Newton's method on steady_gls_residual with a finite-difference
+    Jacobian (columns grouped by a distance-2 colouring of the node graph)
+    and a sparse direct solve.  Dirichlet velocities are fixed to g."""
+    n = xyz.shape[0]
+    u = np.zeros((n, 3))
+    u[dir_mask] = g[dir_mask]
+    p = np.zeros(n)
+    free_u = ~dir_mask
+    # distance-2 colouring: nodes sharing an element get different colours
+    nbr = [set() for _ in range(n)]
+    for t in tets:
+        for a in t:
+            nbr[a].update(t.tolist())
+    col = -np.ones(n, int)
+    for i in range(n):
+        used = set()
+        for j in nbr[i]:
+            for k in nbr[j]:
+                if col[k] >= 0:
+                    used.add(col[k])
+        c = 0
+        while c in used:
+            c += 1
+        col[i] = c
+
+    def R(u, p):
+        rm, rc = steady_gls_residual(xyz, tets, u, p, mu, rho, C_I, ofaces, onormal, oarea,
+                                     h_out, beta)
+        rm[dir_mask] = 0.0
+        return np.concatenate([rm[:, 0], rm[:, 1], rm[:, 2], rc])
+
+    # unknown vector: u_x, u_y, u_z at free nodes (kept full, Dirichlet rows identity), p
+    hist = []
+    for _ in range(max_it):
+        r = R(u, p)
+        hist.append(float(np.linalg.norm(r)))
+        if hist[-1] <= tol * max(hist[0], 1e-300):
+            break
+        rows, cols, vals = [], [], []
+        for c in range(col.max() + 1):
+            sel = np.nonzero(col == c)[0]
+            for f in range(4):
+                eps = 1e-7 * (1.0 + (np.abs(u).max() if f < 3 else np.abs(p).max()))
+                du, dp = u.copy(), p.copy()
+                if f < 3:
+                    du[sel, f] += eps
+                else:
+                    dp[sel] += eps
+                d = (R(du, dp) - r) / eps
+                for i in sel:
+                    nb = np.fromiter(nbr[i], int)
+                    for ff in range(4):
+                        rr = ff * n + nb
+                        rows.append(rr)
+                        cols.append(np.full(nb.size, f * n + i))
+                        vals.append(d[rr])
+        J = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(4 * n, 4 * n))
+        # Dirichlet velocity unknowns: identity rows and columns
+        dmask = np.concatenate([dir_mask, dir_mask, dir_mask, np.zeros(n, bool)])
+        keep = sp.diags((~dmask).astype(float))
+        J = (keep @ J @ keep + sp.diags(dmask.astype(float))).tocsc()
+        x = spla.spsolve(J, -r)
+        u[free_u] += np.stack([x[:n], x[n:2 * n], x[2 * n:3 * n]], axis=1)[free_u]
+        p += x[3 * n:]
+    return u, p, hist
