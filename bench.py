@@ -1,36 +1,42 @@
 #!/usr/bin/env python3
 """Benchmark of the HB-GLS hot path on one MI355X.
 
-Workload: synthetic Glenn-like T-junction (two inlets r = 0.5 meeting
-head-on, outlet r = 0.6, lattice-carved P1 mesh with h = 3/70: 158,688
-nodes, 848,252 tetrahedra), K = 10 harmonics (21 samples), seeded inflow
-waveforms at Re = 500, one resistance outlet, rho = 1.06, mu = 0.04, FP64.
+Workload (default): the synthetic curved branching artery, three bifurcation
+generations with radii 2.0, 1.26, 0.79 and 0.50, lattice-carved P1 mesh
+with h = 0.062: 1,255,132 nodes and 7,046,522 tetrahedra; K = 10 harmonics
+(21 samples); seeded root inflow waveform at Re = 500 on the root diameter;
+eight resistance outlets; rho = 1.06, mu = 0.04; FP64.  (--workload
+tjunction runs the Glenn-like T-junction instead: 158,688 nodes.)
+
+Setup (untimed): the mesh, and the plain start: the steady (K = 0) solve,
+Reynolds number ramped 0.5 -> 1, broadcast to all harmonics.
 
 A step is one pass of the whole hot path: one inexact Newton step of
-hb_newton_solve (HB residual; Jacobi diagonal and per-node time blocks;
-GMRES to eta = 0.03 or the iteration cap, each iteration one Jacobian-vector
-product with its time-axis transforms, element and face kernels and
-scatter; the Newton update), continuing from the previous step's state.
-The state before the first timed step is the plain start (a bounded K = 0
-solve broadcast to all harmonics) advanced by the warm-up steps.
+hb_newton_solve (HB residual; mean-flow multigrid set-up; GMRES to
+eta = 0.03 or the iteration cap, each iteration one Jacobian-vector product
+with its time-axis transforms, element and face kernels and scatter, and one
+preconditioner application; the Newton update).  The warm-up steps and the
+timed steps are each one hb_newton_solve call continuing from the plain
+start with its residual as the reference, so the pseudo step evolves as in
+a single solve.
 
 The line reports:
-  value        Jacobian-vector throughput inside the timed steps,
-               4 n N x (operator applications) / (operator time), with the
+  value        Jacobian-vector throughput inside the timed FP64 steps,
+               4 n N x (operator applications) / (operator time), the
                operator time from HIP events on the solve stream;
-  ms_per_step  wall time per Newton step;
-  jv_public    throughput of the public modal hb_jvp entry point;
-  tm_step_jv   one time-marching step's exact Jv (hb_tm_jvp) on the same
-               mesh, and how many of them one HB Jv costs;
-  tm_vs_hb     the paper's comparison on the Womersley pipe: the GLS
-               time-marching solver marched period by period against the
-               HB solve (wall time, cycle-to-cycle change, difference);
-  time_to_1e8  a complete FP64 solve to 1e-8 of the Womersley-pipe workload
-               (1,911 nodes, K = 2) from its plain start;
+  ms_per_step  wall time per FP64 Newton step;
+  mixed        the same steps with the FP32 Jacobian-vector products and
+               Krylov basis (HB_MIXED), and their state's difference from
+               the FP64 state;
+  jv_public    the public hb_jvp entry point (FP64 and FP32), per stage;
+  time_to_1e8  complete solves to 1e-8 of the plain start's residual, FP64
+               and mixed: the Womersley pipe (1,911 nodes, K = 2) and the
+               T-junction on the coarse lattice (14,191 nodes, K = 10);
   roofline     the element Jacobian-vector kernel against the FP64 vector
-               peak, its duration from HIP events on its launch stream;
-  cpu_baseline the CPU oracle's Jacobian-vector throughput on a bounded
-               sample of the same workload.
+               peak (its duration from HIP events on its launch stream;
+               FP64 operations per lane from rocprofv3 counters);
+  cpu_baseline the CPU oracle's exact Jacobian-vector product on a bounded
+               sample of the same workload, one process and 8 processes.
 """
 from __future__ import annotations
 
@@ -50,27 +56,41 @@ METRIC = "HB Jv throughput (GDOF-modes/s) + time to 1e-8 HB residual, mixed vs F
 PRECISIONS = {"fp64": 0, "mixed": 1, "f32_basis": 2}
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
-# FP64 operations per (tetrahedron, sample) lane of the element kernels,
-# counted from their source (fused multiply-add = 2).
-ELEM_FLOPS = {"exact": 1680, "paper": 970, "residual": 1040}
+# FP64 operations per (tetrahedron, sample) lane of the exact-Jv element
+# kernel: counted by rocprofv3 (FP64 VALU instructions of each kind x 64
+# lanes, FMA = 2) and, for comparison, the survey-style estimate of the
+# algorithm (primal + tangent).
+ELEM_FLOPS_SURVEY = 2700
+ELEM_FLOPS = {"sha256_prefix": "85dde60c62f4d23e", "per_tet_sample": 1953.5,
+              "source": "rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes (FMA = 2), "
+                        "profiles/k_elem_jvp_exact_branching_K10_counters.md"}
+# HBM bytes per launch of the FP64 exact-Jv element kernel, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain
+# copy of known size; valid while the element-kernel source hashes to the
+# recorded value and for the recorded workload.
+ELEM_TRAFFIC = {"sha256_prefix": "85dde60c62f4d23e", "fetch_kib": 3502931, "write_kib": 9538025,
+                "fetch_scale": 2.0, "write_scale": 1.0, "n_nodes": 1255132, "n_tets": 7046522,
+                "K": 10, "profile": "profiles/k_elem_jvp_exact_branching_K10_counters.md"}
 
 
-# HBM bytes per launch of the FP64 exact-Jv element kernel at the benchmark
-# size, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) counters,
-# each scale read off a plain 1 GiB device copy; valid while the
-# element-kernel source section hashes to the recorded value.
-ELEM_TRAFFIC = {"sha256_prefix": "85dde60c62f4d23e", "fetch_kib": 394036, "write_kib": 1193487,
-                "fetch_scale": 2.0, "write_scale": 1.0, "n_nodes": 158688, "n_tets": 848252,
-                "K": 10, "profile": "profiles/k_elem_jvp_exact_tjunction_K10_traffic.md"}
-
-
-def elem_traffic(n, ne, K):
+def _elem_source_hash():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2411_14315_amd", "csrc", "hb_kernels.hip")).read()
     a = src.index("// ------------------------------------------------------------- elements")
     b = src.index("// --------------------------------------------------------------- faces")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def elem_flops_per_lane():
+    f = ELEM_FLOPS
+    if f["sha256_prefix"] is not None and f["sha256_prefix"] != _elem_source_hash():
+        return None, None
+    return f["per_tet_sample"], f["source"]
+
+
+def elem_traffic(n, ne, K):
     t = ELEM_TRAFFIC
-    if (hashlib.sha256(src[a:b].encode()).hexdigest()[:16] != t["sha256_prefix"]
+    if (t is None or t["sha256_prefix"] != _elem_source_hash()
             or (n, ne, K) != (t["n_nodes"], t["n_tets"], t["K"])):
         return None, None
     rd = t["fetch_kib"] * 1024 * t["fetch_scale"]
@@ -78,106 +98,132 @@ def elem_traffic(n, ne, K):
     return rd + wr, {"read_bytes": rd, "write_bytes": wr, "source": t["profile"]}
 
 
-def elem_bytes(n, ne, N, kind):
-    """Algorithmic HBM bytes of one element-kernel launch: node samples read
-    once (7 channels of state, 7 of direction for Jv), accumulator rows
-    read-modify-written once (7 channels), geometry (20 doubles: each lane
-    of a quad reads its own node gradient) and
+def elem_bytes(n, ne, N):
+    """Algorithmic HBM bytes of one exact-Jv element-kernel launch: node
+    samples read once (7 channels of state, 7 of direction), accumulator rows
+    read-modify-written once (7 channels), geometry (20 doubles) and
     connectivity (4 int32) once per tetrahedron."""
-    node_ch = 14 if kind != "residual" else 7
-    return 8.0 * n * N * (node_ch + 2 * 7) + ne * (20 * 8 + 4 * 4)
+    return 8.0 * n * N * (14 + 2 * 7) + ne * (20 * 8 + 4 * 4)
 
 
-def cpu_baseline(P, Y, V, budget_s=30.0):
+# ------------------------------------------------------------ CPU baseline
+_CPU = {}
+
+
+def _cpu_rows(rows):
+    from oracle import residual as res
+    c = _CPU
+    t = time.perf_counter()
+    res.jvp_samples(c["om"], c["prm"], c["y"], c["v"], c["hs"], c["R"], c["H"], rows=rows)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(P, Y, V, budget_s=20.0, workers=8):
     """Oracle exact Jv on a bounded sample: the rows of a contiguous block of
-    nodes (all elements touching them), timed, scaled to the full mesh."""
-    from oracle import api, fem, residual as res, spectral
+    nodes (and every element touching them), timed in one process, then the
+    same rows split over `workers` processes; scaled to the whole mesh by
+    element count."""
+    import multiprocessing as mp
+    from oracle import api, fem, spectral
     om = fem.from_mesh(P.mesh)
     prm = P.params
-    y = api.samples_of(om, prm, Y, P.dirichlet)
-    v = spectral.to_samples(V, prm.K)
-    H = api.H_of(prm)
-    hs = api.h_samples(prm, P.outlet_h)
-    frac = 0.02
+    _CPU.update(om=om, prm=prm, y=api.samples_of(om, prm, Y, P.dirichlet),
+                v=spectral.to_samples(V, prm.K), hs=api.h_samples(prm, P.outlet_h), R=P.outlet_R,
+                H=api.H_of(prm))
+    frac = 0.002
     while True:
         rows = np.arange(int(frac * om.n))
         mark = np.zeros(om.n, bool)
         mark[rows] = True
         nel = int(mark[om.tets].any(axis=1).sum())
-        t = time.perf_counter()
-        res.jvp_samples(om, prm, y, v, hs, P.outlet_R, H, rows=rows)
-        dt = time.perf_counter() - t
-        if dt > 0.25 * budget_s or frac >= 0.5:
+        dt = _cpu_rows(rows)
+        if dt > 0.4 * budget_s or frac >= 0.5:
             break
         frac = min(0.5, frac * max(2.0, 0.5 * budget_s / max(dt, 1e-3)))
-    t_full = dt * om.ne / nel
-    return {"value": 4 * om.n * prm.N / t_full / 1e9, "unit": "GDOF-modes/s", "cores": 1,
-            "kind": "oracle",
+    dofs = 4 * om.n * prm.N
+    one = dofs / (dt * om.ne / nel) / 1e9
+    chunks = np.array_split(rows, workers)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(_cpu_rows, [c[:8] for c in chunks])      # start the workers
+        t = time.perf_counter()
+        pool.map(_cpu_rows, chunks)
+        dtp = time.perf_counter() - t
+    par = dofs / (dtp * om.ne / nel) / 1e9
+    return {"value": one, "unit": "GDOF-modes/s", "cores": 1, "kind": "oracle",
             "sample": f"exact Jv rows of {rows.size} nodes ({nel} of {om.ne} tetrahedra, "
-                      f"{dt:.1f} s), scaled by element count"}
+                      f"{dt:.1f} s in one process), scaled by element count",
+            "parallel": {"value": par, "cores": workers, "seconds": dtp,
+                         "sample": f"the same rows in {workers} processes"}}
 
 
-def tm_step_jv(hbl, torch, P, gm, Y0, V, st, reps):
-    """Exact Jv of one time-marching step (hb_tm_jvp: one time level, the
-    mean modes of the HB state and direction as the step's state and
-    direction, dt = T/200, omega-hat = 2 pi / T) on the same mesh, timed
-    with HIP events on the launch stream."""
-    n = P.mesh.n_nodes
-    y = Y0[:, 0].contiguous()
-    v = V[:, 0].contiguous()
-    a_old = torch.zeros((3, n), dtype=torch.float64, device="cuda:0")
-    g = torch.from_numpy(np.ascontiguousarray(P.dirichlet[:, 0])).to("cuda:0")
-    h = np.ascontiguousarray(P.outlet_h[:, 0])
-    tm = hbl.TmStep(P.params.period / 200, 2 * np.pi / P.params.period, y.clone(), a_old, g, h,
-                    P.outlet_R)
-    jv = torch.empty_like(v)
-    for _ in range(5):
-        hbl.tm_jvp(gm, P.params, tm, y, v, jv)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        hbl.tm_jvp(gm, P.params, tm, y, v, jv)
-    e1.record(st)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return {"ms": ms, "value": 4 * n / (ms * 1e-3) / 1e9, "unit": "GDOF/s"}
+# ------------------------------------------------------------ workloads
+def make_problem(workload):
+    from hbinputs.problems import c2_tjunction, c3_branching
+    if workload == "branching":
+        return c3_branching(), "branching_artery"
+    return c2_tjunction(K=10), "tjunction_glenn_like"
 
 
-def womersley_time_to_solution(hbl, torch, log, precision="fp64"):
-    """Complete FP64 solve of the Womersley-pipe workload to 1e-8 from its
-    plain start (K = 0 solve broadcast), after one untimed warm-up solve."""
+def plain_start(hbl, torch, P, gm, log, ramp=(0.5, 1.0), max_newton=150):
+    """Steady (K = 0) solve with the Reynolds number ramped through `ramp`
+    (fractions of the inflow), broadcast to every harmonic."""
     from dataclasses import replace
-    from hbinputs.problems import c1_womersley
-    P = c1_womersley()
+    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")  # noqa: E731
+    n = P.mesh.n_nodes
+    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
+    reps = []
+    for k, s in enumerate(ramp):
+        bc0 = hbl.BC(to(s * P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
+        last = k == len(ramp) - 1
+        r = hbl.newton_solve(gm, replace(P.params, K=0), bc0, Ys,
+                             hbl.SolveOptions(rtol=1e-9, max_newton=max_newton if last else 20,
+                                              max_gmres=500, precond=hbl.HB_PREC_MEANFLOW,
+                                              amg_cycles=2),
+                             raise_on_noconv=False)
+        reps.append(r)
+        log(f"plain start, inflow x{s}: {r['newton_iters']} Newton, {r['gmres_iters']} GMRES, "
+            f"|r| {r['r0']:.3e} -> {r['r_final']:.3e} ({r['wall_s']:.1f} s)")
+    Y0 = torch.zeros((4, P.params.N, n), dtype=torch.float64, device="cuda:0")
+    Y0[:, 0] = Ys[:, 0]
+    return Y0, reps
+
+
+def solve_opts(hbl, **kw):
+    base = dict(max_gmres=300, precond=hbl.HB_PREC_MEANFLOW, amg_cycles=2)
+    base.update(kw)
+    return hbl.SolveOptions(**base)
+
+
+def time_to_solution(hbl, torch, log, which, precision):
+    """Complete solve to 1e-8 of the plain start's residual (after one untimed
+    warm-up solve); the plain start's own time is reported beside it."""
+    from hbinputs.problems import c1_womersley, c2_tjunction
+    P = c1_womersley() if which == "womersley_pipe" else c2_tjunction(K=10, h=0.1)
     prm = P.params
-    n, N = P.mesh.n_nodes, prm.N
     gm = hbl.Mesh.from_mesh(P.mesh)
     to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")  # noqa: E731
     bc = hbl.BC(to(P.dirichlet), P.outlet_h, P.outlet_R)
-    bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], None)
     res = {}
-    for rep_i in range(2):
+    for _ in range(2):
         torch.cuda.synchronize()
         t = time.time()
-        Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
-        r0 = hbl.newton_solve(gm, replace(prm, K=0), bc0, Ys,
-                              hbl.SolveOptions(rtol=1e-10, max_newton=60, max_gmres=500))
+        Y, reps = plain_start(hbl, torch, P, gm, lambda *a: None, ramp=(1.0,), max_newton=200)
         t_plain = time.time() - t
-        Y = torch.zeros((4, N, n), dtype=torch.float64, device="cuda:0")
-        Y[:, 0] = Ys[:, 0]
         t = time.time()
-        r = hbl.newton_solve(gm, prm, bc, Y, hbl.SolveOptions(
-            rtol=1e-8, max_newton=300, max_gmres=500,
-            precision=PRECISIONS[precision]),
-            raise_on_noconv=False)
+        r = hbl.newton_solve(gm, prm, bc, Y, solve_opts(hbl, rtol=1e-8, max_newton=300,
+                                                        max_gmres=1000,
+                                                        precision=PRECISIONS[precision]),
+                             raise_on_noconv=False)
         t_solve = time.time() - t
-        res = {"workload": "womersley_pipe", "precision": precision, "n_nodes": n, "K": prm.K,
-               "seconds": t_solve, "plain_start_seconds": t_plain,
+        res = {"workload": which, "precision": precision, "n_nodes": P.mesh.n_nodes,
+               "K": prm.K, "seconds": t_solve, "plain_start_seconds": t_plain,
                "total_seconds": t_solve + t_plain, "newton_iters": r["newton_iters"],
                "gmres_iters": r["gmres_iters"], "status": r["status"],
-               "r_final_rel": r["r_final"] / r["r0"]}
-    log(f"womersley pipe time to 1e-8: {res}")
+               "r_final_rel": r["r_final"] / r["r0"], "mass_defect": r["mass_defect"],
+               "plain_start_status": reps[-1]["status"]}
+    log(f"time to 1e-8: {res}")
+    gm.close()
     return res
 
 
@@ -347,63 +393,6 @@ def learned_warm_start(torch, log, n_train, n_test, K=2):
     return out
 
 
-def branching_leg(hbl, torch, log, steps=3, plain_newton=10):
-    """Branching artery (1,255,132 nodes, 7,046,522 tets, K = 10, eight
-    resistance outlets): public Jv in FP64 and FP32, then `steps` inexact
-    Newton steps from the same plain start in FP64, HB_MIXED and
-    HB_F32_BASIS, with the reduced-precision states compared to the FP64
-    state after the same steps."""
-    from dataclasses import replace
-    from hbinputs.problems import c3_branching
-    t = time.time()
-    P = c3_branching()
-    log(f"branching artery mesh: {P.mesh.n_nodes} nodes, {P.mesh.n_tets} tets, {time.time() - t:.1f} s")
-    prm = P.params
-    n, N = P.mesh.n_nodes, prm.N
-    gm = hbl.Mesh.from_mesh(P.mesh)
-    to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")  # noqa: E731
-    bc = hbl.BC(to(P.dirichlet), P.outlet_h, P.outlet_R)
-    bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
-    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
-    hbl.newton_solve(gm, replace(prm, K=0), bc0, Ys,
-                     hbl.SolveOptions(rtol=1e-10, max_newton=plain_newton, max_gmres=300),
-                     raise_on_noconv=False)
-    Y0 = torch.zeros((4, N, n), dtype=torch.float64, device="cuda:0")
-    Y0[:, 0] = Ys[:, 0]
-    dofs = 4.0 * n * N
-    V = Y0.clone()
-    out = {"workload": "branching_artery", "n_nodes": n, "n_tets": P.mesh.n_tets, "K": prm.K,
-           "outlets": int(P.outlet_R.size)}
-    for name, Vx in (("jv_fp64", V), ("jv_fp32", V.float())):
-        for _ in range(3):
-            hbl.jvp(gm, prm, bc, Y0, Vx)
-        torch.cuda.synchronize()
-        t = time.time()
-        for _ in range(10):
-            hbl.jvp(gm, prm, bc, Y0, Vx)
-        torch.cuda.synchronize()
-        ms = (time.time() - t) / 10 * 1e3
-        out[name] = {"ms": ms, "gdofs": dofs / (ms * 1e-3) / 1e9}
-    states = {}
-    for p_ in ("fp64", "mixed", "f32_basis"):
-        opts = hbl.SolveOptions(rtol=1e-30, max_newton=1, max_gmres=300, precision=PRECISIONS[p_])
-        Y = Y0.clone()
-        torch.cuda.synchronize()
-        t = time.time()
-        reps = [hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False) for _ in range(steps)]
-        torch.cuda.synchronize()
-        states[p_] = Y
-        out[p_] = {"ms_per_step": (time.time() - t) / steps * 1e3,
-                   "gmres_iters_per_step": [r["gmres_iters"] for r in reps],
-                   "residual_per_step": [r["r_final"] for r in reps]}
-        if p_ != "fp64":
-            out[p_]["state_rel_diff_vs_fp64"] = float(
-                torch.linalg.norm(Y - states["fp64"]) / torch.linalg.norm(states["fp64"]))
-    log(f"branching artery: {out}")
-    gm.close()
-    return out
-
-
 def cfl_study(hbl, torch, log, workload="tjunction", cfls=(0.25, 1.0, 4.0, 16.0), steps=40):
     """Pseudo-time step study (Section 2.3 sets dt ~ h_c / u_c): FP64 Newton
     steps from the plain start with the pseudo step held fixed at
@@ -455,21 +444,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--jv-reps", type=int, default=20)
-    ap.add_argument("--mode", choices=["solve", "jv"], default="solve")
+    ap.add_argument("--workload", choices=["branching", "tjunction"], default="branching")
+    ap.add_argument("--jv-reps", type=int, default=10)
+    ap.add_argument("--max-gmres", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-time-to-solution", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
-    ap.add_argument("--h", type=float, default=3.0 / 70.0)
-    ap.add_argument("--K", type=int, default=10)
+    ap.add_argument("--jv-only", action="store_true",
+                    help="setup, then only public hb_jvp calls (for kernel profiling)")
+    ap.add_argument("--plain-newton", type=int, default=150,
+                    help="Newton steps of the plain start's last stage (0: no plain start; a "
+                         "seeded state stands in, for kernel profiling)")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--plain-newton", type=int, default=30)
-    ap.add_argument("--max-gmres", type=int, default=300)
-    ap.add_argument("--cfl-max", type=float, default=0.0)
-    ap.add_argument("--precision", choices=["fp64", "mixed", "f32_basis", "both"], default="both",
-                    help="'both': FP64 plus the two reduced-precision Krylov forms")
-    ap.add_argument("--no-time-to-solution", action="store_true")
-    ap.add_argument("--learned-train", type=int, default=384,
+    ap.add_argument("--learned-train", type=int, default=0,
                     help="training solutions of the learned warm-start leg (0: skip it)")
     ap.add_argument("--learned-test", type=int, default=12)
     ap.add_argument("--cfl-study", choices=["tjunction", "womersley"], default=None,
@@ -477,12 +466,10 @@ def main():
     ap.add_argument("--periodicity", choices=["tjunction", "womersley"], default=None,
                     help="march the workload period by period with the time-marching solver "
                          "and report the cycle-to-cycle change (skips the main bench)")
-    ap.add_argument("--tm-periods", type=int, default=6,
+    ap.add_argument("--h", type=float, default=3.0 / 70.0)
+    ap.add_argument("--tm-periods", type=int, default=0,
                     help="periods of the time-marching comparison on the Womersley pipe (0: off)")
     ap.add_argument("--tm-spp", type=int, default=50, help="time-marching steps per period")
-    ap.add_argument("--branching", type=int, default=0,
-                    help="Newton steps of the branching-artery leg (0: skip it; the mesh "
-                         "takes about a minute to generate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
@@ -491,14 +478,14 @@ def main():
 
     import torch
     import paper_2411_14315_amd as hbl
-    from hbinputs.problems import c2_tjunction, seeded_state
+    from hbinputs.problems import seeded_state
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
     if args.periodicity:
         print(json.dumps({"periodicity": periodicity(hbl, torch, log, args.periodicity,
-                                                     h=args.h, periods=args.tm_periods)}),
+                                                     h=args.h, periods=args.tm_periods or 8)}),
               flush=True)
         return
     if args.cfl_study:
@@ -507,10 +494,10 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    P = c2_tjunction(K=args.K, h=args.h)
+    P, wname = make_problem(args.workload)
     prm = P.params
     n, ne, N = P.mesh.n_nodes, P.mesh.n_tets, prm.N
-    log(f"workload: {n} nodes, {ne} tets, N={N} ({time.time() - t0:.1f} s to generate)")
+    log(f"workload {wname}: {n} nodes, {ne} tets, N={N} ({time.time() - t0:.1f} s to generate)")
     gm = hbl.Mesh.from_mesh(P.mesh)
     to = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
     bc = hbl.BC(to(P.dirichlet), P.outlet_h, P.outlet_R)
@@ -523,145 +510,131 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calib_copy_mib} MiB read + written")
 
-    # plain start: a bounded steady K = 0 solve broadcast to all harmonics
-    from dataclasses import replace
-    p0 = replace(prm, K=0)
-    bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
-    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device=dev)
     t = time.time()
-    rep0 = hbl.newton_solve(gm, p0, bc0, Ys,
-                            hbl.SolveOptions(rtol=1e-6, max_newton=args.plain_newton,
-                                             max_gmres=300, cfl_max=args.cfl_max,
-                                             verbose=int(args.verbose)),
-                            raise_on_noconv=False)
+    if args.plain_newton > 0:
+        Y0, preps = plain_start(hbl, torch, P, gm, log, max_newton=args.plain_newton)
+    else:
+        Y0, preps = to(seeded_state(P, 0)), [{"newton_iters": 0, "status": -4, "r_final": None}]
     plain_s = time.time() - t
-    log(f"plain start: {rep0['newton_iters']} Newton, {rep0['gmres_iters']} GMRES, "
-        f"|r| {rep0['r0']:.3e} -> {rep0['r_final']:.3e}, {plain_s:.2f} s")
-    Y0 = torch.zeros((4, N, n), dtype=torch.float64, device=dev)
-    Y0[:, 0] = Ys[:, 0]
     V = to(seeded_state(P, 1))
+    dofs = 4 * n * N
 
-    # public hb_jvp microbenchmark with stage timing
+    # public hb_jvp with stage timing (FP64 and FP32 directions)
     gm.set_timing(True)
     st = torch.cuda.current_stream()
-    JV = torch.empty_like(V)
-    for _ in range(5):
-        hbl.jvp(gm, prm, bc, Y0, V, JV)
-    torch.cuda.synchronize()
-    stages = {k: 0.0 for k in hbl.Mesh.STAGES}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    tot = 0.0
-    for _ in range(args.jv_reps):
-        e0.record(st)
-        hbl.jvp(gm, prm, bc, Y0, V, JV)
-        e1.record(st)
-        tt = gm.last_timings()
-        for k in stages:
-            stages[k] += tt[k] / args.jv_reps
-        e1.synchronize()
-        tot += e0.elapsed_time(e1) / args.jv_reps
-    V32 = V.float()
-    JV32 = torch.empty_like(V32)
-    for _ in range(5):
-        hbl.jvp(gm, prm, bc, Y0, V32, JV32)
-    torch.cuda.synchronize()
-    stages32 = {k: 0.0 for k in hbl.Mesh.STAGES}
-    tot32 = 0.0
-    for _ in range(args.jv_reps):
-        e0.record(st)
-        hbl.jvp(gm, prm, bc, Y0, V32, JV32)
-        e1.record(st)
-        tt = gm.last_timings()
-        for k in stages32:
-            stages32[k] += tt[k] / args.jv_reps
-        e1.synchronize()
-        tot32 += e0.elapsed_time(e1) / args.jv_reps
+
+    def public_jv(Vx):
+        JVx = torch.empty_like(Vx)
+        for _ in range(3):
+            hbl.jvp(gm, prm, bc, Y0, Vx, JVx)
+        torch.cuda.synchronize()
+        stages = {k: 0.0 for k in hbl.Mesh.STAGES}
+        tot = 0.0
+        for _ in range(args.jv_reps):
+            e0.record(st)
+            hbl.jvp(gm, prm, bc, Y0, Vx, JVx)
+            e1.record(st)
+            tt = gm.last_timings()
+            for k in stages:
+                stages[k] += tt[k] / args.jv_reps
+            e1.synchronize()
+            tot += e0.elapsed_time(e1) / args.jv_reps
+        return tot, stages
+
+    tot, stages = public_jv(V)
+    tot32, stages32 = public_jv(V.float())
     gm.set_timing(False)
-    dofs = 4 * n * N
-    jv_public = dofs / (tot * 1e-3) / 1e9
-    log(f"hb_jvp: {tot:.3f} ms ({jv_public:.2f} GDOF-modes/s); stages {stages}")
-    tm_jv = tm_step_jv(hbl, torch, P, gm, Y0, V, st, args.jv_reps)
-    log(f"hb_tm_jvp (one time-marching step's Jv): {tm_jv['ms']:.3f} ms; "
-        f"HB Jv / step Jv = {tot / tm_jv['ms']:.1f}")
+    log(f"hb_jvp: {tot:.3f} ms ({dofs / tot / 1e6:.2f} GDOF-modes/s); stages {stages}")
+    if args.jv_only:
+        gm.close()
+        return
 
     elem_ms = stages["element"]
-    flops = ELEM_FLOPS["exact"] * ne * N
-    eb = elem_bytes(n, ne, N, "exact")
-    traffic, traffic_detail = elem_traffic(n, ne, args.K)
+    per_lane, flop_src = elem_flops_per_lane()
+    flops = (per_lane or 0.0) * ne * N
     roofline = {"bound": "alu", "achieved": flops / (elem_ms * 1e-3) / 1e12,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": flops / (elem_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                "traffic": traffic,
-                "kernel": "k_elem_jvp_exact", "kernel_ms": elem_ms,
-                "hbm_algorithmic_GBs": eb / (elem_ms * 1e-3) / 1e9}
+                "traffic": None, "kernel": "k_elem_block<1,double> (exact Jv)",
+                "kernel_ms": elem_ms, "flop_per_lane": per_lane, "flop_source": flop_src,
+                "frac_survey_count": ELEM_FLOPS_SURVEY * ne * N / (elem_ms * 1e-3) / 1e12
+                / FP64_PEAK_TFLOPS,
+                "hbm_algorithmic_GBs": elem_bytes(n, ne, N) / (elem_ms * 1e-3) / 1e9}
+    traffic, traffic_detail = elem_traffic(n, ne, prm.K)
     if traffic is not None:
+        roofline["traffic"] = traffic
         roofline["traffic_detail"] = dict(traffic_detail,
                                           hbm_measured_GBs=traffic / (elem_ms * 1e-3) / 1e9)
 
-    out = {"metric": METRIC, "unit": "GDOF-modes/s", "n_gpus": 1, "higher_is_better": True,
-           "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "tjunction_glenn_like", "n_nodes": n, "n_tets": ne, "K": args.K,
-                      "samples": N, "reynolds": 500, "outlet": "resistance",
-                      "precision": "fp64", "rtol": 1e-8}}
-    if args.mode == "jv":
-        out.update({"value": jv_public, "steps": args.jv_reps, "warmup": 5, "ms_per_step": tot,
-                    "step": "one public hb_jvp call"})
-    else:
-        def newton_steps(precision):
-            opts = hbl.SolveOptions(rtol=1e-30, max_newton=1, max_gmres=args.max_gmres,
-                                    cfl_max=args.cfl_max, verbose=int(args.verbose),
-                                    precision=precision)
-            Y = Y0.clone()
-            for _ in range(args.warmup):
-                hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False)
-            torch.cuda.synchronize()
-            reps = []
-            t = time.time()
-            for _ in range(args.steps):
-                reps.append(hbl.newton_solve(gm, prm, bc, Y, opts, raise_on_noconv=False))
-            torch.cuda.synchronize()
-            wall = (time.time() - t) / args.steps
-            n_jv = sum(r["n_jv"] for r in reps)
-            jv_ms = sum(r["jv_ms"] for r in reps)
-            return {"jv_gdofs": dofs * n_jv / (jv_ms * 1e-3) / 1e9, "ms_per_step": wall * 1e3,
-                    "gmres_iters_per_step": [r["gmres_iters"] for r in reps],
-                    "residual_per_step": [r["r_final"] for r in reps],
-                    "jv_ms_avg": jv_ms / max(n_jv, 1)}
-        main_prec = "fp64" if args.precision == "both" else args.precision
-        res = {p_: newton_steps(PRECISIONS[p_])
-               for p_ in (["fp64", "mixed", "f32_basis"] if args.precision == "both"
-                          else [main_prec])}
-        r0 = res[main_prec]
-        out.update({"value": r0["jv_gdofs"], "steps": args.steps, "warmup": args.warmup,
-                    "ms_per_step": r0["ms_per_step"],
-                    "step": f"one {main_prec.upper()} inexact Newton step (residual, "
-                            "preconditioner, GMRES eta=0.03 with exact Jv, update) on the "
-                            "T-junction",
-                    "gmres_iters_per_step": r0["gmres_iters_per_step"],
-                    "residual_per_step": r0["residual_per_step"],
-                    "plain_start_s": plain_s, "jv_ms_avg": r0["jv_ms_avg"]})
-        for p_ in ("mixed", "f32_basis"):
-            if p_ in res and main_prec != p_:
-                out[p_] = res[p_]
-        if not args.no_time_to_solution:
-            out["time_to_1e8"] = {p_: womersley_time_to_solution(hbl, torch, log, p_)
-                                  for p_ in res}
-        if args.tm_periods > 0:
-            out["tm_vs_hb"] = tm_vs_hb(hbl, torch, log, args.tm_periods, args.tm_spp)
-        if args.branching > 0:
-            out["branching_artery"] = branching_leg(hbl, torch, log, args.branching)
-        if args.learned_train > 0:
-            out["learned_warm_start"] = learned_warm_start(torch, log, args.learned_train,
-                                                           args.learned_test)
-    out["jv_public"] = {"value": jv_public, "unit": "GDOF-modes/s", "ms": tot,
+    r_ref = hbl.newton_solve(gm, prm, bc, Y0.clone(), hbl.SolveOptions(max_newton=0),
+                             raise_on_noconv=False)["r0"]
+
+    def newton_steps(precision):
+        Y = Y0.clone()
+        if args.warmup:
+            hbl.newton_solve(gm, prm, bc, Y, solve_opts(hbl, rtol=1e-30, r_ref=r_ref,
+                                                        max_newton=args.warmup,
+                                                        max_gmres=args.max_gmres,
+                                                        precision=precision,
+                                                        verbose=int(args.verbose)),
+                             raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.time()
+        rep = hbl.newton_solve(gm, prm, bc, Y, solve_opts(hbl, rtol=1e-30, r_ref=r_ref,
+                                                          max_newton=args.steps,
+                                                          max_gmres=args.max_gmres,
+                                                          precision=precision,
+                                                          verbose=int(args.verbose)),
+                               raise_on_noconv=False)
+        torch.cuda.synchronize()
+        wall = (time.time() - t) / args.steps
+        return Y, {"jv_gdofs": dofs * rep["n_jv"] / (rep["jv_ms"] * 1e-3) / 1e9,
+                   "ms_per_step": wall * 1e3, "gmres_iters": rep["gmres_iters"],
+                   "gmres_per_step": rep["gmres_iters"] / args.steps,
+                   "jv_ms_avg": rep["jv_ms"] / max(rep["n_jv"], 1),
+                   "precond_ms_avg": rep["pc_ms"] / max(rep["n_jv"], 1),
+                   "residual_rel": rep["r_final"] / r_ref}
+
+    Y64, r64 = newton_steps(PRECISIONS["fp64"])
+    log(f"FP64 Newton steps: {r64}")
+    out = {"metric": METRIC, "value": r64["jv_gdofs"], "unit": "GDOF-modes/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
+           "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": wname, "n_nodes": n, "n_tets": ne, "K": prm.K, "samples": N,
+                      "reynolds": 500, "outlets": "resistance x" + str(len(P.outlet_R)),
+                      "precision": "fp64", "preconditioner": "mean-flow multigrid"},
+           "step": "one inexact Newton step (residual, mean-flow multigrid set-up, GMRES "
+                   "eta=0.03 with the exact Jv, update), continuing one solve",
+           "fp64": r64, "plain_start_s": plain_s,
+           "plain_start": {"newton_iters": sum(r["newton_iters"] for r in preps),
+                           "status": preps[-1]["status"],
+                           "r_final": preps[-1]["r_final"]},
+           "multigrid_levels": hbl.precond_levels(gm)}
+    if not args.no_mixed:
+        Ym, rm = newton_steps(PRECISIONS["mixed"])
+        rm["state_rel_diff_vs_fp64"] = float(torch.linalg.norm(Ym - Y64) / torch.linalg.norm(Y64))
+        rm["speedup_per_step_vs_fp64"] = r64["ms_per_step"] / rm["ms_per_step"]
+        out["mixed"] = rm
+        log(f"mixed Newton steps: {rm}")
+    out["jv_public"] = {"value": dofs / (tot * 1e-3) / 1e9, "unit": "GDOF-modes/s", "ms": tot,
                         "stages_ms": stages}
     out["jv_public_fp32"] = {"value": dofs / (tot32 * 1e-3) / 1e9, "unit": "GDOF-modes/s",
                              "ms": tot32, "stages_ms": stages32}
-    tm_jv["hb_jv_over_step_jv"] = tot / tm_jv["ms"]
-    out["tm_step_jv"] = tm_jv
     out["roofline"] = roofline
+    if not args.no_time_to_solution:
+        out["time_to_1e8"] = {f"{w}:{p_}": time_to_solution(hbl, torch, log, w, p_)
+                              for w in ("womersley_pipe", "tjunction_h0.1")
+                              for p_ in ("fp64", "mixed")}
+    if args.tm_periods > 0:
+        out["tm_vs_hb"] = tm_vs_hb(hbl, torch, log, args.tm_periods, args.tm_spp)
+    if args.learned_train > 0:
+        out["learned_warm_start"] = learned_warm_start(torch, log, args.learned_train,
+                                                       args.learned_test)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, Y0.cpu().numpy(), V.cpu().numpy())
+    gm.close()
     print(json.dumps(out), flush=True)
 
 

@@ -279,6 +279,9 @@ typedef struct {
                               1 a node with its free neighbours                 */
   double amg_coarse_weight; /* HB_PREC_MEANFLOW: weight of the coarse-level
                                correction (0: 0.7)                              */
+  int32_t amg_smoother; /* HB_PREC_MEANFLOW: 0 damped block Jacobi, 1 symmetric
+                           block Gauss-Seidel over colour classes              */
+  int32_t amg_wcycle;   /* HB_PREC_MEANFLOW: 0 V-cycles, 1 W-cycles            */
 } hb_solve_opts;
 
 typedef struct {
@@ -289,9 +292,13 @@ typedef struct {
   double r_final;
   double r_ref;
   double wall_s;
-  double jv_ms;    /* total time spent in Krylov operator applications */
+  double jv_ms;    /* total time spent in the Jacobian-vector products of the
+                      Krylov operator (transforms, element and face
+                      kernels, scatter; with graphs also Gram-Schmidt) */
   int32_t n_jv;
   int32_t rejected; /* Newton steps taken damped (alpha < 1)          */
+  double pc_ms;    /* total time in preconditioner applications inside the
+                      Krylov operator (not part of jv_ms)             */
   double mass_defect; /* at the returned state: max over samples of
                          |sum_A r^c_A(t_n)| (the net boundary outflow, since
                          sum_A N_A = 1) over max over samples of the total
@@ -336,6 +343,9 @@ typedef struct {
   int32_t coarse_max;    /* 1..256                                            */
   int32_t aggregation;   /* 0 pairwise matching twice, 1 node + neighbours    */
   double coarse_weight;  /* weight of the coarse-level correction, (0, 2]     */
+  int32_t smoother;      /* 0 damped block Jacobi, 1 symmetric block Gauss-
+                            Seidel over colour classes (weight unused)        */
+  int32_t wcycle;        /* 0 V-cycle, 1 W-cycle                              */
 } hb_precond_opts;
 int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
                      double shift, const hb_precond_opts* opts, int32_t op, const double* X,

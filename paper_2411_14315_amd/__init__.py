@@ -66,20 +66,21 @@ class _Opts(C.Structure):
                 ("cfl_max", C.c_double), ("graphs", C.c_int32), ("amg_sweeps", C.c_int32),
                 ("amg_cycles", C.c_int32), ("amg_weight", C.c_double),
                 ("reject_ratio", C.c_double), ("dt_growth", C.c_double),
-                ("amg_aggregation", C.c_int32), ("amg_coarse_weight", C.c_double)]
+                ("amg_aggregation", C.c_int32), ("amg_coarse_weight", C.c_double),
+                ("amg_smoother", C.c_int32), ("amg_wcycle", C.c_int32)]
 
 
 class _PcOpts(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("cycles", C.c_int32), ("weight", C.c_double),
                 ("coarse_max", C.c_int32), ("aggregation", C.c_int32),
-                ("coarse_weight", C.c_double)]
+                ("coarse_weight", C.c_double), ("smoother", C.c_int32), ("wcycle", C.c_int32)]
 
 
 class _Report(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("status", C.c_int32),
                 ("r0", C.c_double), ("r_final", C.c_double), ("r_ref", C.c_double),
                 ("wall_s", C.c_double), ("jv_ms", C.c_double), ("n_jv", C.c_int32),
-                ("rejected", C.c_int32), ("mass_defect", C.c_double)]
+                ("rejected", C.c_int32), ("pc_ms", C.c_double), ("mass_defect", C.c_double)]
 
 
 _lib = None
@@ -436,13 +437,15 @@ class SolveOptions:
     dt_growth: float = 0.0     # least pseudo-step growth after a non-increasing step (0: 1)
     amg_aggregation: int = 0   # HB_PREC_MEANFLOW: 0 pairwise matching twice, 1 node + neighbours
     amg_coarse_weight: float = 0.0  # HB_PREC_MEANFLOW: coarse-correction weight (0: 0.7)
+    amg_smoother: int = 0      # HB_PREC_MEANFLOW: 0 block Jacobi, 1 block Gauss-Seidel
+    amg_wcycle: int = 0        # HB_PREC_MEANFLOW: 0 V-cycles, 1 W-cycles
 
     def _c(self):
         return _Opts(self.rtol, self.r_ref, self.gmres_eta, self.cfl, self.c1, self.restart,
                      self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose,
                      self.precond, self.cfl_max, self.graphs, self.amg_sweeps, self.amg_cycles,
                      self.amg_weight, self.reject_ratio, self.dt_growth, self.amg_aggregation,
-                     self.amg_coarse_weight)
+                     self.amg_coarse_weight, self.amg_smoother, self.amg_wcycle)
 
 
 def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None,
@@ -463,7 +466,8 @@ def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None
 
 def precond_apply(mesh: Mesh, params, bc: BC, Y, X, shift: float = 0.0, op: str = "inverse",
                   sweeps: int = 2, cycles: int = 1, weight: float = 0.7, coarse_max: int = 64,
-                  aggregation: int = 0, coarse_weight: float = 0.7, OUT=None, stream=None):
+                  aggregation: int = 0, coarse_weight: float = 0.7, smoother: int = 0,
+                  wcycle: int = 0, OUT=None, stream=None):
     """The mean-flow modal preconditioner at the state Y: ``op="operator"``
     applies its operator A, ``op="inverse"`` its multigrid approximation of
     A^-1 (modal (4, N, n) arrays; see hb_precond_apply)."""
@@ -479,7 +483,7 @@ def precond_apply(mesh: Mesh, params, bc: BC, Y, X, shift: float = 0.0, op: str 
         raise HBError(HB_ERR_ARG, f"unknown op {op!r}")
     outp = _arg(OUT, "OUT", shp, device=Y.device)
     o = _PcOpts(int(sweeps), int(cycles), float(weight), int(coarse_max), int(aggregation),
-                float(coarse_weight))
+                float(coarse_weight), int(smoother), int(wcycle))
     pc, bcc = p._c(), bc._c(mesh, p.N)
     _check(load().hb_precond_apply(mesh._h, C.byref(pc), C.byref(bcc), yp, float(shift),
                                    C.byref(o), op_, xp, outp, _stream(stream)))

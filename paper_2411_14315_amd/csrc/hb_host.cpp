@@ -83,7 +83,7 @@ struct SolverBufs {
   double* hpin = nullptr;  // pinned host copies of each Arnoldi step's coefficients
   size_t hpin_n = 0;
   hipEvent_t evh[2] = {};  // Arnoldi step completion (ping-pong)
-  hipEvent_t evj[4] = {};  // Jv timing: two (start, end) pairs
+  hipEvent_t evj[6] = {};  // operator timing: two (start, after preconditioner, end) triples
   // Arnoldi steps captured as HIP graphs, one per step index, valid while
   // every pointer and size they were captured with (key) is unchanged.
   std::vector<uintptr_t> gkey;
@@ -852,7 +852,8 @@ int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc,
   if (!std::isfinite(shift) || shift < 0) return fail(HB_ERR_ARG, "shift must be finite, >= 0");
   if (o->sweeps < 1 || o->cycles < 1 || !(o->weight > 0 && o->weight <= 1) || o->coarse_max < 1 ||
       o->coarse_max > 256 || (o->aggregation != 0 && o->aggregation != 1) ||
-      !(o->coarse_weight > 0 && o->coarse_weight <= 2))
+      !(o->coarse_weight > 0 && o->coarse_weight <= 2) || (o->smoother != 0 && o->smoother != 1) ||
+      (o->wcycle != 0 && o->wcycle != 1))
     return fail(HB_ERR_ARG, "bad preconditioner options");
   hb_mesh* m = const_cast<hb_mesh*>(mesh);
   hipStream_t st = (hipStream_t)stream;
@@ -867,7 +868,7 @@ int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc,
   HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab,
                                                 w.Sy.as<double>(), nullptr, nullptr, 0, st));
   HB_CHECK(hb::precond_setup(m->pc, m->dm, p, w.Sy.as<double>(), shift, o->sweeps, o->cycles,
-                             o->weight, o->coarse_weight, st));
+                             o->weight, o->coarse_weight, o->smoother, o->wcycle, st));
   // X (Dirichlet velocity entries dropped) to samples [n][7][N]
   HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, X, bc->dirichlet, 1, tab,
                                                 w.Sv.as<double>(), nullptr, nullptr, 0, st));
@@ -966,6 +967,7 @@ struct Solver {
   const double* hist_a = nullptr;
   double hist_cu = 0.0, hist_ca = 0.0;
   double jv_ms = 0.0;
+  double pc_ms = 0.0;
   int n_jv = 0;
   bool jv_pending[2] = {false, false};
 
@@ -1075,10 +1077,18 @@ struct Solver {
     }
     if (use_pc) {
       HB_CHECK((hb::precond_apply<T, double>(m->pc, m->dm.n, q, 4, m->pcz.as<double>(), st)));
+      if (timed_apply) {
+        int rc = timer_mid(pr);
+        if (rc) return rc;
+      }
       HB_CHECK((hb::prepare_direction<double, T>(m->dm, N, m->pcz.as<double>(), 4, nullptr,
                                                  nullptr, 1, tab, Sv, acc, s.dQ,
                                                  m->dm.n_out * N, st)));
     } else {
+      if (timed_apply) {
+        int rc = timer_mid(pr);
+        if (rc) return rc;
+      }
       HB_CHECK(hb::prepare_direction<T, T>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1, tab,
                                            Sv, acc, s.dQ, m->dm.n_out * N, st));
     }
@@ -1106,11 +1116,16 @@ struct Solver {
       int rc = collect_jv(pr);
       if (rc) return rc;
     }
-    HB_CHECK(hipEventRecord(sb->evj[2 * pr], st));
+    HB_CHECK(hipEventRecord(sb->evj[3 * pr], st));
+    return HB_OK;
+  }
+  // between the preconditioner and the Jacobian-vector product
+  int timer_mid(int pr) {
+    HB_CHECK(hipEventRecord(sb->evj[3 * pr + 1], st));
     return HB_OK;
   }
   int timer_stop(int pr) {
-    HB_CHECK(hipEventRecord(sb->evj[2 * pr + 1], st));
+    HB_CHECK(hipEventRecord(sb->evj[3 * pr + 2], st));
     jv_pending[pr] = true;
     ++n_jv;
     return HB_OK;
@@ -1129,10 +1144,18 @@ struct Solver {
     }
     if (use_pc) {
       HB_CHECK((hb::precond_apply<T, double>(m->pc, m->dm.n, q, 4, m->pcz.as<double>(), st)));
+      if (timed_apply) {
+        int rc = timer_mid(pr);
+        if (rc) return rc;
+      }
       HB_CHECK((hb::prepare_direction<double, double>(m->dm, N, m->pcz.as<double>(), 4, nullptr,
                                                       nullptr, 1, tab, Sv, acc, s.dQ,
                                                       m->dm.n_out * N, st)));
     } else {
+      if (timed_apply) {
+        int rc = timer_mid(pr);
+        if (rc) return rc;
+      }
       HB_CHECK((hb::prepare_direction<T, double>(m->dm, N, q, 4, w.dinv.as<double>(), binv, 1,
                                                   tab, Sv, acc, s.dQ, m->dm.n_out * N, st)));
     }
@@ -1167,10 +1190,12 @@ struct Solver {
 
   // Adds the duration of a recorded Jv (waits for it).
   int collect_jv(int pr) {
-    HB_CHECK(hipEventSynchronize(sb->evj[2 * pr + 1]));
-    float ms = 0.f;
-    HB_CHECK(hipEventElapsedTime(&ms, sb->evj[2 * pr], sb->evj[2 * pr + 1]));
+    HB_CHECK(hipEventSynchronize(sb->evj[3 * pr + 2]));
+    float ms = 0.f, mp = 0.f;
+    HB_CHECK(hipEventElapsedTime(&mp, sb->evj[3 * pr], sb->evj[3 * pr + 1]));
+    HB_CHECK(hipEventElapsedTime(&ms, sb->evj[3 * pr + 1], sb->evj[3 * pr + 2]));
     jv_ms += ms;
+    pc_ms += mp;
     jv_pending[pr] = false;
     return HB_OK;
   }
@@ -1270,6 +1295,8 @@ struct Solver {
         }
         const int pr = n_jv & 1;
         int rc2 = timer_start(pr);
+        if (rc2) return rc2;
+        rc2 = timer_mid(pr);
         if (rc2) return rc2;
         HB_CHECK(hipGraphLaunch(sb->gexec[j], st));
         rc2 = timer_stop(pr);
@@ -1477,7 +1504,7 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
     const Phys pj = make_phys(prm, shift);
     if (S.use_pc) {
       HB_CHECK(hb::precond_setup(m->pc, m->dm, pj, w.Sy.as<double>(), shift, amg_nu, amg_cyc,
-                                 amg_w, amg_g, st));
+                                 amg_w, amg_g, opts->amg_smoother, opts->amg_wcycle, st));
     } else {
       const int nc = S.binv ? 4 : 2;
       HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), m->dm.n * nc * N, st));
@@ -1575,6 +1602,7 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   HB_CHECK(hipStreamSynchronize(st));
   report->status = status;
   report->jv_ms = S.jv_ms;
+  report->pc_ms = S.pc_ms;
   report->n_jv = S.n_jv;
   report->wall_s =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1674,7 +1702,7 @@ int tm_march_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y, d
       pj.tau_add = pp.tau_add;
       if (S.use_pc) {
         HB_CHECK(hb::precond_setup(m->pc, m->dm, pj, w.Sy.as<double>(), pj.shift, 2, 1, 0.7, 0.7,
-                                   st));
+                                   0, 0, st));
       } else {
         HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), n * 2, st));
         HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), 0, st));
@@ -1759,7 +1787,9 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
     return fail(HB_ERR_ARG, "reject_ratio must be finite (0, < 0 or >= 1), dt_growth >= 0");
   if (opts->amg_sweeps < 0 || opts->amg_cycles < 0 || !(opts->amg_weight >= 0) ||
       opts->amg_weight > 1 || (opts->amg_aggregation != 0 && opts->amg_aggregation != 1) ||
-      !(opts->amg_coarse_weight >= 0) || opts->amg_coarse_weight > 2)
+      !(opts->amg_coarse_weight >= 0) || opts->amg_coarse_weight > 2 ||
+      (opts->amg_smoother != 0 && opts->amg_smoother != 1) ||
+      (opts->amg_wcycle != 0 && opts->amg_wcycle != 1))
     return fail(HB_ERR_ARG, "bad multigrid options");
   hb_mesh* m = const_cast<hb_mesh*>(mesh);
   hipStream_t st = (hipStream_t)stream;

@@ -30,9 +30,11 @@
 // matching (or of a node and its free neighbours), piecewise-constant
 // transfer with a weighted coarse correction, Galerkin coarse operators (the 17
 // coefficient fields above are summed over aggregate pairs, so every level
-// has the same form), damped block-Jacobi smoothing with the closed-form
-// inverse of the 4 x 4 nodal block, and a dense complex inverse on the
-// coarsest level.  All K+1 modes are processed by every launch: the matrix
+// has the same form), smoothing with the closed-form inverse of the 4 x 4
+// nodal block, and a dense complex inverse on the
+// coarsest level (damped block Jacobi, or symmetric block Gauss-Seidel over
+// the colour classes of each level's graph; V- or W-cycles).  All K+1 modes
+// are processed by every launch: the matrix
 // coefficients are read once per node pair and applied to the K+1 mode
 // vectors of the neighbour.
 #include "hb_internal.h"
@@ -326,6 +328,54 @@ k_pc_rows(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restri
   store4(y, gid, out);
 }
 
+// Gauss-Seidel sweep over one colour class (no two rows of a class are
+// neighbours, so the class updates x in place without races): for each row
+// i of the class and each mode, x_i += D_i^-1 (b - A x)_i.
+__global__ void __launch_bounds__(PBLK)
+k_pc_gs(int64_t nrows, const int32_t* __restrict__ rows, const int32_t* __restrict__ rowptr,
+        const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
+        const double* __restrict__ val, Coef c, const double* __restrict__ b, double* x) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= nrows * c.nm) return;
+  const int64_t li = gid / c.nm;
+  const int m = (int)(gid - li * c.nm);
+  const int64_t i = rows[li];
+  const double s = m * c.omega;
+  cplx r[4];
+  load4(b, i * c.nm + m, r);
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    const int64_t j = col[k];
+    const PairOp o = pair_op(val + (int64_t)k * PC_NF, c, s);
+    cplx xj[4];
+    load4(x, j * c.nm + m, xj);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) r[f] = csub(r[f], cadd(cmul(o.kap, xj[f]), cmul(o.g[f], xj[3])));
+    r[3] = csub(r[3], cadd(cadd(cmul(o.d[0], xj[0]), cmul(o.d[1], xj[1])),
+                           cadd(cmul(o.d[2], xj[2]), {o.l * xj[3].re, o.l * xj[3].im})));
+  }
+  const PairOp o = pair_op(val + (int64_t)diag[i] * PC_NF, c, s);
+  cplx sp = r[3], den = {o.l, 0.0};
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    sp = csub(sp, cdiv(cmul(o.d[f], r[f]), o.kap));
+    den = csub(den, cdiv(cmul(o.d[f], o.g[f]), o.kap));
+  }
+  cplx e[4];
+  e[3] = cdiv(sp, den);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) e[f] = cdiv(csub(r[f], cmul(o.g[f], e[3])), o.kap);
+  cplx xi[4];
+  load4(x, i * c.nm + m, xi);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) xi[f] = cadd(xi[f], e[f]);
+  store4(x, i * c.nm + m, xi);
+}
+
+__global__ void __launch_bounds__(PBLK) k_pc_zero(int64_t len, double* __restrict__ x) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid < len) x[gid] = 0.0;
+}
+
 // bc[I] = sum of r over the members of aggregate I (all modes).
 __global__ void __launch_bounds__(PBLK)
 k_pc_restrict(int64_t nc, int nm, const int32_t* __restrict__ mptr,
@@ -576,6 +626,9 @@ struct PcLevel {
   // coarse node, and the fine entries of each coarse entry
   DeviceArray<int32_t> agg, mptr, mem, gptr, gsrc;
   DeviceArray<double> x, x2, b, r;
+  // colour classes of the level's graph (Gauss-Seidel smoothing)
+  DeviceArray<int32_t> crows;
+  std::vector<int64_t> cptr;
 };
 
 struct Precond {
@@ -590,6 +643,8 @@ struct Precond {
   int cycles = 1;
   double wj = 0.7;
   double gamma = 1.0;  // weight of the coarse-level correction
+  int smoother = 0;    // 0 damped block Jacobi, 1 symmetric block Gauss-Seidel
+  int wcycle = 0;      // 1: two coarse-level cycles per level (W-cycle)
   Coef coef{};
   size_t bytes() const {
     size_t b = cs.bytes() + dense.bytes() + work.bytes() + inv.bytes();
@@ -701,6 +756,34 @@ void coarsen_graph(const HostGraph& g, const std::vector<int32_t>& agg, int64_t 
   }
 }
 
+// Greedy colouring of a graph (self loops ignored): classes of rows that
+// share no edge, as a permutation grouped by colour.
+void colour_classes(const HostGraph& g, std::vector<int64_t>& cptr, std::vector<int32_t>& rows) {
+  const int64_t n = (int64_t)g.rowptr.size() - 1;
+  std::vector<int32_t> colour(n, -1);
+  std::vector<int64_t> mark;
+  int ncol = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k) {
+      const int32_t c = colour[g.col[k]];
+      if (c >= 0) {
+        if ((int)mark.size() <= c) mark.resize(c + 1, -1);
+        mark[c] = i;
+      }
+    }
+    int c = 0;
+    while (c < (int)mark.size() && mark[c] == i) ++c;
+    colour[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  cptr.assign(ncol + 1, 0);
+  for (int64_t i = 0; i < n; ++i) ++cptr[colour[i] + 1];
+  for (int c = 0; c < ncol; ++c) cptr[c + 1] += cptr[c];
+  rows.resize(n);
+  std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+  for (int64_t i = 0; i < n; ++i) rows[fill[colour[i]]++] = (int32_t)i;
+}
+
 // One pass of pairwise matching: each node in turn is paired with its first
 // unmatched neighbour (or left alone); pairs are numbered in order.
 int64_t match_pairs(const HostGraph& g, std::vector<int32_t>& agg) {
@@ -774,6 +857,11 @@ hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int co
     if ((e = upload(L.rowptr, g.rowptr)) || (e = upload(L.col, g.col)) || (e = upload(L.diag, diag)))
       return e;
     if ((e = L.val.ensure((size_t)L.nnz * PC_NF))) return e;
+    {
+      std::vector<int32_t> rows;
+      colour_classes(g, L.cptr, rows);
+      if ((e = upload(L.crows, rows))) return e;
+    }
     if (nl <= coarse_max || level >= 15) break;
     std::vector<int32_t> agg, mptr, mem;
     const int64_t na = pairwise ? aggregate_pairs(g, agg) : aggregate(g, agg);
@@ -844,10 +932,12 @@ hipError_t ensure_modes(Precond* pc, int N) {
 }  // namespace
 
 hipError_t precond_setup(Precond* pc, const DevMesh& m, const Phys& p, const double* Sy,
-                         double sigma, int nu, int cycles, double wj, double gamma,
-                         hipStream_t st) {
+                         double sigma, int nu, int cycles, double wj, double gamma, int smoother,
+                         int wcycle, hipStream_t st) {
   hipError_t e = ensure_modes(pc, p.N);
   if (e != hipSuccess) return e;
+  pc->smoother = smoother;
+  pc->wcycle = wcycle;
   pc->nu = nu;
   pc->cycles = cycles;
   pc->wj = wj;
@@ -887,13 +977,27 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
     return hipGetLastError();
   }
   const unsigned g = nblk(L.n * nm);
-  auto sweep = [&](bool from_zero) {
+  auto sweep = [&](bool from_zero, bool reverse) {
+    if (pc->smoother == 1) {
+      if (from_zero)
+        hipLaunchKernelGGL(k_pc_zero, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st,
+                           L.n * nm * 8, L.x.p);
+      const int nc = (int)L.cptr.size() - 1;
+      for (int q = 0; q < nc; ++q) {
+        const int c = reverse ? nc - 1 - q : q;
+        const int64_t nr = L.cptr[c + 1] - L.cptr[c];
+        hipLaunchKernelGGL(k_pc_gs, dim3(nblk(nr * nm)), dim3(PBLK), 0, st, nr,
+                           L.crows.p + L.cptr[c], L.rowptr.p, L.col.p, L.diag.p, L.val.p,
+                           pc->coef, L.b.p, L.x.p);
+      }
+      return;
+    }
     hipLaunchKernelGGL(k_pc_rows<2>, dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
                        L.diag.p, L.val.p, pc->coef, L.b.p, from_zero ? nullptr : L.x.p, L.x2.p,
                        pc->wj);
     std::swap(L.x.p, L.x2.p);
   };
-  for (int k = 0; k < pc->nu; ++k) sweep(zero_start && k == 0);
+  for (int k = 0; k < pc->nu; ++k) sweep(zero_start && k == 0, false);
   hipLaunchKernelGGL(k_pc_rows<1>, dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
                      L.diag.p, L.val.p, pc->coef, L.b.p, L.x.p, L.r.p, 0.0);
   PcLevel& C = pc->lv[l + 1];
@@ -901,9 +1005,13 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
                      L.mptr.p, L.mem.p, L.r.p, C.b.p);
   hipError_t e = vcycle(pc, l + 1, true, st);
   if (e != hipSuccess) return e;
+  if (pc->wcycle && l + 2 < pc->lv.size()) {
+    e = vcycle(pc, l + 1, false, st);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_pc_prolong, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st, L.n, nm, L.agg.p,
                      C.x.p, L.x.p, pc->gamma);
-  for (int k = 0; k < pc->nu; ++k) sweep(false);
+  for (int k = 0; k < pc->nu; ++k) sweep(false, true);
   return hipGetLastError();
 }
 

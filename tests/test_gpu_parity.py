@@ -298,3 +298,41 @@ def test_graph_replay_matches_eager(c1, precision):
         assert out[2][0]["gmres_iters"] == out[0][0]["gmres_iters"]
         assert diff <= max(1e-12, 10.0 * spread), step
         Y = dev(out[2][1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reduced_tjunction_solve_matches_oracle(precision):
+    """The T-junction workload on the coarse lattice (h = 0.1, 14,191 nodes,
+    K = 10, Re = 500, resistance outlet): the GPU solve from its own plain
+    start to 1e-12 of the initial residual (mean-flow multigrid) reaches the
+    oracle's stored root (modal values at 2,048 seeded nodes, 1e-10), and
+    the oracle's residual at the GPU solution is below 1e-8 of the oracle's
+    initial residual (the certificate)."""
+    path = os.path.join(HERE, "golden", "c2_reduced_solution.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle root not written (tests/golden/make_golden.py c2)")
+    from dataclasses import replace
+    g = np.load(path)
+    c = Case(c2_tjunction(K=10, h=0.1))
+    P = c.P
+    n = c.om.n
+    bc0 = hbl.BC(dev(P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
+    Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda")
+    rep0 = hbl.newton_solve(c.gm, replace(P.params, K=0), bc0, Ys,
+                            hbl.SolveOptions(rtol=1e-13, max_newton=200, max_gmres=1000,
+                                             precond=hbl.HB_PREC_MEANFLOW, amg_cycles=2))
+    assert rep0["status"] == 0
+    Y = torch.zeros((4, P.params.N, n), dtype=torch.float64, device="cuda")
+    Y[:, 0] = Ys[:, 0]
+    prec = hbl.HB_MIXED if precision == "mixed" else hbl.HB_F64
+    rep = hbl.newton_solve(c.gm, P.params, c.bc, Y,
+                           hbl.SolveOptions(rtol=1e-12, max_newton=200, max_gmres=1000,
+                                            precond=hbl.HB_PREC_MEANFLOW, amg_cycles=2,
+                                            precision=prec))
+    print(precision, {k: rep[k] for k in ("newton_iters", "gmres_iters", "r0", "r_final",
+                                          "wall_s", "mass_defect")}, flush=True)
+    assert rep["status"] == 0
+    Yg = host(Y)
+    assert rel(Yg[:, :, g["nodes"]], g["Y"]) <= TOL
+    r = api.residual_modal(c.om, P.params, Yg, P.dirichlet, P.outlet_h, P.outlet_R)
+    assert api.sample_norm(r, P.params.K) <= 1e-8 * float(g["r0"])
