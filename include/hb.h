@@ -282,6 +282,10 @@ typedef struct {
   int32_t amg_smoother; /* HB_PREC_MEANFLOW: 0 damped block Jacobi, 1 symmetric
                            block Gauss-Seidel over colour classes              */
   int32_t amg_wcycle;   /* HB_PREC_MEANFLOW: 0 V-cycles, 1 W-cycles            */
+  int32_t amg_fp32;     /* HB_PREC_MEANFLOW: 0 FP64 cycles; 1 smoothing, residuals
+                           and transfers on FP32 vectors and coefficients (the
+                           coefficients are assembled in FP64 and rounded; the
+                           coarsest-level inverse stays FP64)                  */
 } hb_solve_opts;
 
 typedef struct {
@@ -346,6 +350,7 @@ typedef struct {
   int32_t smoother;      /* 0 damped block Jacobi, 1 symmetric block Gauss-
                             Seidel over colour classes (weight unused)        */
   int32_t wcycle;        /* 0 V-cycle, 1 W-cycle                              */
+  int32_t fp32;          /* 0 FP64 cycles, 1 FP32 cycles (as amg_fp32)        */
 } hb_precond_opts;
 int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, const double* Y,
                      double shift, const hb_precond_opts* opts, int32_t op, const double* X,

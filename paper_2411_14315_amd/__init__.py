@@ -67,13 +67,15 @@ class _Opts(C.Structure):
                 ("amg_cycles", C.c_int32), ("amg_weight", C.c_double),
                 ("reject_ratio", C.c_double), ("dt_growth", C.c_double),
                 ("amg_aggregation", C.c_int32), ("amg_coarse_weight", C.c_double),
-                ("amg_smoother", C.c_int32), ("amg_wcycle", C.c_int32)]
+                ("amg_smoother", C.c_int32), ("amg_wcycle", C.c_int32),
+                ("amg_fp32", C.c_int32)]
 
 
 class _PcOpts(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("cycles", C.c_int32), ("weight", C.c_double),
                 ("coarse_max", C.c_int32), ("aggregation", C.c_int32),
-                ("coarse_weight", C.c_double), ("smoother", C.c_int32), ("wcycle", C.c_int32)]
+                ("coarse_weight", C.c_double), ("smoother", C.c_int32), ("wcycle", C.c_int32),
+                ("fp32", C.c_int32)]
 
 
 class _Report(C.Structure):
@@ -439,13 +441,14 @@ class SolveOptions:
     amg_coarse_weight: float = 0.0  # HB_PREC_MEANFLOW: coarse-correction weight (0: 0.7)
     amg_smoother: int = 0      # HB_PREC_MEANFLOW: 0 block Jacobi, 1 block Gauss-Seidel
     amg_wcycle: int = 0        # HB_PREC_MEANFLOW: 0 V-cycles, 1 W-cycles
+    amg_fp32: int = 0          # HB_PREC_MEANFLOW: 1 cycles on FP32 vectors and coefficients
 
     def _c(self):
         return _Opts(self.rtol, self.r_ref, self.gmres_eta, self.cfl, self.c1, self.restart,
                      self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose,
                      self.precond, self.cfl_max, self.graphs, self.amg_sweeps, self.amg_cycles,
                      self.amg_weight, self.reject_ratio, self.dt_growth, self.amg_aggregation,
-                     self.amg_coarse_weight, self.amg_smoother, self.amg_wcycle)
+                     self.amg_coarse_weight, self.amg_smoother, self.amg_wcycle, self.amg_fp32)
 
 
 def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None,
@@ -467,7 +470,7 @@ def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None
 def precond_apply(mesh: Mesh, params, bc: BC, Y, X, shift: float = 0.0, op: str = "inverse",
                   sweeps: int = 2, cycles: int = 1, weight: float = 0.7, coarse_max: int = 64,
                   aggregation: int = 0, coarse_weight: float = 0.7, smoother: int = 0,
-                  wcycle: int = 0, OUT=None, stream=None):
+                  wcycle: int = 0, fp32: int = 0, OUT=None, stream=None):
     """The mean-flow modal preconditioner at the state Y: ``op="operator"``
     applies its operator A, ``op="inverse"`` its multigrid approximation of
     A^-1 (modal (4, N, n) arrays; see hb_precond_apply)."""
@@ -483,7 +486,7 @@ def precond_apply(mesh: Mesh, params, bc: BC, Y, X, shift: float = 0.0, op: str 
         raise HBError(HB_ERR_ARG, f"unknown op {op!r}")
     outp = _arg(OUT, "OUT", shp, device=Y.device)
     o = _PcOpts(int(sweeps), int(cycles), float(weight), int(coarse_max), int(aggregation),
-                float(coarse_weight), int(smoother), int(wcycle))
+                float(coarse_weight), int(smoother), int(wcycle), int(fp32))
     pc, bcc = p._c(), bc._c(mesh, p.N)
     _check(load().hb_precond_apply(mesh._h, C.byref(pc), C.byref(bcc), yp, float(shift),
                                    C.byref(o), op_, xp, outp, _stream(stream)))

@@ -372,7 +372,7 @@ int ensure_precond(hb_mesh* m, int coarse_max, int pairwise, int N) {
   return HB_OK;
 }
 
-constexpr int kCoarseMax = 64;
+constexpr int kCoarseMax = 24;
 
 }  // namespace
 
@@ -853,7 +853,7 @@ int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc,
   if (o->sweeps < 1 || o->cycles < 1 || !(o->weight > 0 && o->weight <= 1) || o->coarse_max < 1 ||
       o->coarse_max > 256 || (o->aggregation != 0 && o->aggregation != 1) ||
       !(o->coarse_weight > 0 && o->coarse_weight <= 2) || (o->smoother != 0 && o->smoother != 1) ||
-      (o->wcycle != 0 && o->wcycle != 1))
+      (o->wcycle != 0 && o->wcycle != 1) || (o->fp32 != 0 && o->fp32 != 1))
     return fail(HB_ERR_ARG, "bad preconditioner options");
   hb_mesh* m = const_cast<hb_mesh*>(mesh);
   hipStream_t st = (hipStream_t)stream;
@@ -868,7 +868,7 @@ int hb_precond_apply(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc,
   HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, Y, bc->dirichlet, 0, tab,
                                                 w.Sy.as<double>(), nullptr, nullptr, 0, st));
   HB_CHECK(hb::precond_setup(m->pc, m->dm, p, w.Sy.as<double>(), shift, o->sweeps, o->cycles,
-                             o->weight, o->coarse_weight, o->smoother, o->wcycle, st));
+                             o->weight, o->coarse_weight, o->smoother, o->wcycle, o->fp32, st));
   // X (Dirichlet velocity entries dropped) to samples [n][7][N]
   HB_CHECK(hb::modal_to_samples<double, double>(m->dm, N, X, bc->dirichlet, 1, tab,
                                                 w.Sv.as<double>(), nullptr, nullptr, 0, st));
@@ -1504,7 +1504,8 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
     const Phys pj = make_phys(prm, shift);
     if (S.use_pc) {
       HB_CHECK(hb::precond_setup(m->pc, m->dm, pj, w.Sy.as<double>(), shift, amg_nu, amg_cyc,
-                                 amg_w, amg_g, opts->amg_smoother, opts->amg_wcycle, st));
+                                 amg_w, amg_g, opts->amg_smoother, opts->amg_wcycle,
+                                 opts->amg_fp32, st));
     } else {
       const int nc = S.binv ? 4 : 2;
       HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), m->dm.n * nc * N, st));
@@ -1702,7 +1703,7 @@ int tm_march_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y, d
       pj.tau_add = pp.tau_add;
       if (S.use_pc) {
         HB_CHECK(hb::precond_setup(m->pc, m->dm, pj, w.Sy.as<double>(), pj.shift, 2, 1, 0.7, 0.7,
-                                   0, 0, st));
+                                   0, 0, 0, st));
       } else {
         HB_CHECK(hb::vec_zero<double>(w.dg.as<double>(), n * 2, st));
         HB_CHECK(hb::elem_jacobi(m->dm, pj, w.Sy.as<double>(), w.dg.as<double>(), 0, st));
@@ -1789,7 +1790,8 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
       opts->amg_weight > 1 || (opts->amg_aggregation != 0 && opts->amg_aggregation != 1) ||
       !(opts->amg_coarse_weight >= 0) || opts->amg_coarse_weight > 2 ||
       (opts->amg_smoother != 0 && opts->amg_smoother != 1) ||
-      (opts->amg_wcycle != 0 && opts->amg_wcycle != 1))
+      (opts->amg_wcycle != 0 && opts->amg_wcycle != 1) ||
+      (opts->amg_fp32 != 0 && opts->amg_fp32 != 1))
     return fail(HB_ERR_ARG, "bad multigrid options");
   hb_mesh* m = const_cast<hb_mesh*>(mesh);
   hipStream_t st = (hipStream_t)stream;

@@ -195,10 +195,11 @@ int precond_levels(const Precond* p, int64_t* sizes, int max);
 // coefficient sigma; nu Jacobi sweeps (weight wj) before and after each
 // coarse correction (weight gamma), `cycles` cycles per application;
 // smoother 0 damped block Jacobi, 1 symmetric block Gauss-Seidel (colour
-// classes; wj unused); wcycle 1 for W-cycles.
+// classes; wj unused); wcycle 1 for W-cycles; fp32 1 for cycles on FP32
+// vectors and coefficients (the coarsest inverse stays FP64).
 hipError_t precond_setup(Precond* pc, const DevMesh& m, const Phys& p, const double* Sy,
                          double sigma, int nu, int cycles, double wj, double gamma, int smoother,
-                         int wcycle, hipStream_t st);
+                         int wcycle, int fp32, hipStream_t st);
 // z [n][4][N] = M^-1 q, q with in_ch channels per node ([n][in_ch][N]).
 template <typename TQ, typename TZ>
 hipError_t precond_apply(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st);

@@ -59,18 +59,28 @@ enum {
 constexpr double QA_ = 0.58541019662496845446137605030969;
 constexpr double QB_ = 0.13819660112501051517954131656344;
 
-struct cplx {
-  double re, im;
+template <typename T>
+struct cplxT {
+  T re, im;
 };
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+template <typename T>
+__device__ __forceinline__ cplxT<T> cmul(cplxT<T> a, cplxT<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
-  const double d = b.re * b.re + b.im * b.im;
+template <typename T>
+__device__ __forceinline__ cplxT<T> cadd(cplxT<T> a, cplxT<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__device__ __forceinline__ cplxT<T> csub(cplxT<T> a, cplxT<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename T>
+__device__ __forceinline__ cplxT<T> cdiv(cplxT<T> a, cplxT<T> b) {
+  const T d = b.re * b.re + b.im * b.im;
   return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
+using cplx = cplxT<double>;
 
 // Position of column c in row r of a CSR graph with sorted columns.
 __device__ __forceinline__ int64_t csr_find(const int32_t* __restrict__ rowptr,
@@ -237,31 +247,38 @@ struct Coef {
   int nm;
 };
 
-// The mode-m coefficients of one node pair.
+// The mode-m coefficients of one node pair (T: arithmetic type, M: the type
+// the coefficients are stored in).
+template <typename T>
 struct PairOp {
-  cplx kap, g[3], d[3];
-  double l;
+  cplxT<T> kap, g[3], d[3];
+  T l;
 };
-__device__ __forceinline__ PairOp pair_op(const double* __restrict__ v, const Coef& c, double s) {
-  PairOp o;
-  o.kap = {v[F_K] + c.sigma * v[F_M] + s * s * c.rho * v[F_T], s * (c.rho * v[F_M] + v[F_XS])};
+template <typename T, typename M>
+__device__ __forceinline__ PairOp<T> pair_op(const M* __restrict__ v, const Coef& c, T s) {
+  PairOp<T> o;
+  const T rho = (T)c.rho;
+  o.kap = {(T)v[F_K] + (T)c.sigma * (T)v[F_M] + s * s * rho * (T)v[F_T],
+           s * (rho * (T)v[F_M] + (T)v[F_XS])};
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    o.g[i] = {v[F_G + i], -s * v[F_GP + i]};
-    o.d[i] = {v[F_D + i], s * v[F_DP + i]};
+    o.g[i] = {(T)v[F_G + i], -s * (T)v[F_GP + i]};
+    o.d[i] = {(T)v[F_D + i], s * (T)v[F_DP + i]};
   }
-  o.l = v[F_L];
+  o.l = (T)v[F_L];
   return o;
 }
 
 // Complex vectors: [node][mode][4][re, im].
-__device__ __forceinline__ void load4(const double* __restrict__ x, int64_t idx, cplx out[4]) {
-  const double* p = x + idx * 8;
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ x, int64_t idx, cplxT<T> out[4]) {
+  const T* p = x + idx * 8;
 #pragma unroll
   for (int f = 0; f < 4; ++f) out[f] = {p[2 * f], p[2 * f + 1]};
 }
-__device__ __forceinline__ void store4(double* __restrict__ x, int64_t idx, const cplx v[4]) {
-  double* p = x + idx * 8;
+template <typename T>
+__device__ __forceinline__ void store4(T* __restrict__ x, int64_t idx, const cplxT<T> v[4]) {
+  T* p = x + idx * 8;
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     p[2 * f] = v[f].re;
@@ -269,38 +286,61 @@ __device__ __forceinline__ void store4(double* __restrict__ x, int64_t idx, cons
   }
 }
 
+// e = D^-1 r for the nodal block D = [kap I, g; d^T, l] (Schur complement on
+// the pressure).
+template <typename T>
+__device__ __forceinline__ void block_solve(const PairOp<T>& o, const cplxT<T> r[4],
+                                            cplxT<T> e[4]) {
+  cplxT<T> sp = r[3], den = {o.l, (T)0};
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    sp = csub(sp, cdiv(cmul(o.d[f], r[f]), o.kap));
+    den = csub(den, cdiv(cmul(o.d[f], o.g[f]), o.kap));
+  }
+  e[3] = cdiv(sp, den);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) e[f] = cdiv(csub(r[f], cmul(o.g[f], e[3])), o.kap);
+}
+
+// acc += A_row(i) x for one mode
+template <typename T, typename M>
+__device__ __forceinline__ void row_apply(int64_t i, int m, const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ col,
+                                          const M* __restrict__ val, const Coef& c, T s,
+                                          const T* __restrict__ x, cplxT<T> acc[4]) {
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    const int64_t j = col[k];
+    const PairOp<T> o = pair_op<T, M>(val + (int64_t)k * PC_NF, c, s);
+    cplxT<T> xj[4];
+    load4(x, j * c.nm + m, xj);
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+      acc[f] = cadd(acc[f], cadd(cmul(o.kap, xj[f]), cmul(o.g[f], xj[3])));
+    acc[3] = cadd(acc[3], cadd(cadd(cmul(o.d[0], xj[0]), cmul(o.d[1], xj[1])),
+                               cadd(cmul(o.d[2], xj[2]), cplxT<T>{o.l * xj[3].re, o.l * xj[3].im})));
+  }
+}
+
 // Row operation on all modes, one lane per (node, mode):
 //   OP 0: y = A x;  OP 1: y = b - A x;
 //   OP 2: y = x + w D^-1 (b - A x) (x = NULL: y = w D^-1 b), D the nodal block.
-template <int OP>
+template <int OP, typename T, typename M>
 __global__ void __launch_bounds__(PBLK)
 k_pc_rows(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-          const int32_t* __restrict__ diag, const double* __restrict__ val, Coef c,
-          const double* __restrict__ b, const double* __restrict__ x, double* __restrict__ y,
-          double wj) {
+          const int32_t* __restrict__ diag, const M* __restrict__ val, Coef c,
+          const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ y, double wj) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= n * c.nm) return;
   const int64_t i = gid / c.nm;
   const int m = (int)(gid - i * c.nm);
-  const double s = m * c.omega;
-  cplx acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  if (x) {
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-      const int64_t j = col[k];
-      const PairOp o = pair_op(val + (int64_t)k * PC_NF, c, s);
-      cplx xj[4];
-      load4(x, j * c.nm + m, xj);
-#pragma unroll
-      for (int f = 0; f < 3; ++f) acc[f] = cadd(acc[f], cadd(cmul(o.kap, xj[f]), cmul(o.g[f], xj[3])));
-      acc[3] = cadd(acc[3], cadd(cadd(cmul(o.d[0], xj[0]), cmul(o.d[1], xj[1])),
-                                 cadd(cmul(o.d[2], xj[2]), {o.l * xj[3].re, o.l * xj[3].im})));
-    }
-  }
+  const T s = (T)(m * c.omega);
+  cplxT<T> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  if (x) row_apply<T, M>(i, m, rowptr, col, val, c, s, x, acc);
   if (OP == 0) {
     store4(y, gid, acc);
     return;
   }
-  cplx r[4];
+  cplxT<T> r[4];
   load4(b, gid, r);
 #pragma unroll
   for (int f = 0; f < 4; ++f) r[f] = csub(r[f], acc[f]);
@@ -308,97 +348,83 @@ k_pc_rows(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restri
     store4(y, gid, r);
     return;
   }
-  // block solve [kap I, g; d^T, l] e = r
-  const PairOp o = pair_op(val + (int64_t)diag[i] * PC_NF, c, s);
-  cplx sp = r[3], den = {o.l, 0.0};
-#pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    sp = csub(sp, cdiv(cmul(o.d[f], r[f]), o.kap));
-    den = csub(den, cdiv(cmul(o.d[f], o.g[f]), o.kap));
-  }
-  cplx e[4];
-  e[3] = cdiv(sp, den);
-#pragma unroll
-  for (int f = 0; f < 3; ++f) e[f] = cdiv(csub(r[f], cmul(o.g[f], e[3])), o.kap);
-  cplx out[4];
+  cplxT<T> e[4];
+  block_solve(pair_op<T, M>(val + (int64_t)diag[i] * PC_NF, c, s), r, e);
+  cplxT<T> out[4];
   if (x) load4(x, gid, out);
-  else out[0] = out[1] = out[2] = out[3] = {0.0, 0.0};
+  else out[0] = out[1] = out[2] = out[3] = {(T)0, (T)0};
+  const T w = (T)wj;
 #pragma unroll
-  for (int f = 0; f < 4; ++f) out[f] = {out[f].re + wj * e[f].re, out[f].im + wj * e[f].im};
+  for (int f = 0; f < 4; ++f) out[f] = {out[f].re + w * e[f].re, out[f].im + w * e[f].im};
   store4(y, gid, out);
 }
 
 // Gauss-Seidel sweep over one colour class (no two rows of a class are
 // neighbours, so the class updates x in place without races): for each row
 // i of the class and each mode, x_i += D_i^-1 (b - A x)_i.
+template <typename T, typename M>
 __global__ void __launch_bounds__(PBLK)
 k_pc_gs(int64_t nrows, const int32_t* __restrict__ rows, const int32_t* __restrict__ rowptr,
         const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
-        const double* __restrict__ val, Coef c, const double* __restrict__ b, double* x) {
+        const M* __restrict__ val, Coef c, const T* __restrict__ b, T* x) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= nrows * c.nm) return;
   const int64_t li = gid / c.nm;
   const int m = (int)(gid - li * c.nm);
   const int64_t i = rows[li];
-  const double s = m * c.omega;
-  cplx r[4];
+  const T s = (T)(m * c.omega);
+  cplxT<T> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  row_apply<T, M>(i, m, rowptr, col, val, c, s, x, acc);
+  cplxT<T> r[4];
   load4(b, i * c.nm + m, r);
-  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const int64_t j = col[k];
-    const PairOp o = pair_op(val + (int64_t)k * PC_NF, c, s);
-    cplx xj[4];
-    load4(x, j * c.nm + m, xj);
 #pragma unroll
-    for (int f = 0; f < 3; ++f) r[f] = csub(r[f], cadd(cmul(o.kap, xj[f]), cmul(o.g[f], xj[3])));
-    r[3] = csub(r[3], cadd(cadd(cmul(o.d[0], xj[0]), cmul(o.d[1], xj[1])),
-                           cadd(cmul(o.d[2], xj[2]), {o.l * xj[3].re, o.l * xj[3].im})));
-  }
-  const PairOp o = pair_op(val + (int64_t)diag[i] * PC_NF, c, s);
-  cplx sp = r[3], den = {o.l, 0.0};
-#pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    sp = csub(sp, cdiv(cmul(o.d[f], r[f]), o.kap));
-    den = csub(den, cdiv(cmul(o.d[f], o.g[f]), o.kap));
-  }
-  cplx e[4];
-  e[3] = cdiv(sp, den);
-#pragma unroll
-  for (int f = 0; f < 3; ++f) e[f] = cdiv(csub(r[f], cmul(o.g[f], e[3])), o.kap);
-  cplx xi[4];
+  for (int f = 0; f < 4; ++f) r[f] = csub(r[f], acc[f]);
+  cplxT<T> e[4];
+  block_solve(pair_op<T, M>(val + (int64_t)diag[i] * PC_NF, c, s), r, e);
+  cplxT<T> xi[4];
   load4(x, i * c.nm + m, xi);
 #pragma unroll
   for (int f = 0; f < 4; ++f) xi[f] = cadd(xi[f], e[f]);
   store4(x, i * c.nm + m, xi);
 }
 
-__global__ void __launch_bounds__(PBLK) k_pc_zero(int64_t len, double* __restrict__ x) {
+template <typename T>
+__global__ void __launch_bounds__(PBLK) k_pc_zero(int64_t len, T* __restrict__ x) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
-  if (gid < len) x[gid] = 0.0;
+  if (gid < len) x[gid] = (T)0;
+}
+
+// FP32 copy of the coefficients for the smoothing and transfer kernels.
+__global__ void __launch_bounds__(PBLK)
+k_pc_narrow(int64_t len, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid < len) b[gid] = (float)a[gid];
 }
 
 // bc[I] = sum of r over the members of aggregate I (all modes).
+template <typename T>
 __global__ void __launch_bounds__(PBLK)
 k_pc_restrict(int64_t nc, int nm, const int32_t* __restrict__ mptr,
-              const int32_t* __restrict__ mem, const double* __restrict__ r,
-              double* __restrict__ bc) {
+              const int32_t* __restrict__ mem, const T* __restrict__ r, T* __restrict__ bc) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= nc * nm * 8) return;
   const int64_t I = gid / (nm * 8);
   const int k = (int)(gid - I * nm * 8);
-  double s = 0.0;
+  T s = (T)0;
   for (int j = mptr[I]; j < mptr[I + 1]; ++j) s += r[(int64_t)mem[j] * nm * 8 + k];
   bc[gid] = s;
 }
 
 // x[i] += gamma xc[agg[i]] (all modes).
+template <typename T>
 __global__ void __launch_bounds__(PBLK)
-k_pc_prolong(int64_t n, int nm, const int32_t* __restrict__ agg, const double* __restrict__ xc,
-             double* __restrict__ x, double gamma) {
+k_pc_prolong(int64_t n, int nm, const int32_t* __restrict__ agg, const T* __restrict__ xc,
+             T* __restrict__ x, double gamma) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= n * nm * 8) return;
   const int64_t i = gid / (nm * 8);
   const int k = (int)(gid - i * nm * 8);
-  x[gid] += gamma * xc[(int64_t)agg[i] * nm * 8 + k];
+  x[gid] += (T)gamma * xc[(int64_t)agg[i] * nm * 8 + k];
 }
 
 // Dense coarsest-level matrices, one per mode: A[m][4I+a][4J+b] (complex,
@@ -420,7 +446,7 @@ k_pc_dense(int64_t nc, const int32_t* __restrict__ rowptr, const int32_t* __rest
   }
   const int64_t I = lo, J = col[k];
   const int64_t D = 4 * nc;
-  const PairOp o = pair_op(val + k * PC_NF, c, m * c.omega);
+  const PairOp<double> o = pair_op<double, double>(val + k * PC_NF, c, m * c.omega);
   double* Am = A + (int64_t)m * D * D * 2;
   auto put = [&](int64_t r, int64_t cc, cplx v) {
     Am[(r * D + cc) * 2] = v.re;
@@ -509,7 +535,7 @@ k_pc_invert(int D, const double* __restrict__ A, double* __restrict__ W,
     const cplx ip = {piv[0], piv[1]};
     for (int cc = threadIdx.x; cc < W2; cc += PBLK) {
       double* a = Wm + ((int64_t)k * W2 + cc) * 2;
-      const cplx v = cmul({a[0], a[1]}, ip);
+      const cplx v = cmul(cplx{a[0], a[1]}, ip);
       a[0] = v.re;
       a[1] = v.im;
     }
@@ -521,7 +547,7 @@ k_pc_invert(int D, const double* __restrict__ A, double* __restrict__ W,
       const double* fr = Wm + ((int64_t)r * W2 + k) * 2;
       const double* pk = Wm + ((int64_t)k * W2 + cc) * 2;
       double* a = Wm + e * 2;
-      const cplx v = csub({a[0], a[1]}, cmul({fr[0], fr[1]}, {pk[0], pk[1]}));
+      const cplx v = csub(cplx{a[0], a[1]}, cmul(cplx{fr[0], fr[1]}, cplx{pk[0], pk[1]}));
       a[0] = v.re;
       a[1] = v.im;
     }
@@ -542,10 +568,11 @@ k_pc_invert(int D, const double* __restrict__ A, double* __restrict__ W,
   }
 }
 
-// x = Ainv_m b on the coarsest level; one lane per (mode, row).
+// x = Ainv_m b on the coarsest level (FP64 arithmetic); one lane per (mode, row).
+template <typename T>
 __global__ void __launch_bounds__(PBLK)
-k_pc_dense_apply(int64_t nc, int nm, const double* __restrict__ Ainv,
-                 const double* __restrict__ b, double* __restrict__ x) {
+k_pc_dense_apply(int64_t nc, int nm, const double* __restrict__ Ainv, const T* __restrict__ b,
+                 T* __restrict__ x) {
   const int64_t D = 4 * nc;
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= D * nm) return;
@@ -556,28 +583,29 @@ k_pc_dense_apply(int64_t nc, int nm, const double* __restrict__ Ainv,
   for (int64_t cc = 0; cc < D; ++cc) {
     const int64_t J = cc >> 2;
     const int f = (int)(cc & 3);
-    const double* bv = b + ((J * nm + m) * 4 + f) * 2;
-    re += Ar[cc * 2] * bv[0] - Ar[cc * 2 + 1] * bv[1];
-    im += Ar[cc * 2] * bv[1] + Ar[cc * 2 + 1] * bv[0];
+    const T* bv = b + ((J * nm + m) * 4 + f) * 2;
+    const double br = (double)bv[0], bi = (double)bv[1];
+    re += Ar[cc * 2] * br - Ar[cc * 2 + 1] * bi;
+    im += Ar[cc * 2] * bi + Ar[cc * 2 + 1] * br;
   }
   const int64_t I = r >> 2;
   const int f = (int)(r & 3);
-  double* xv = x + ((I * nm + m) * 4 + f) * 2;
-  xv[0] = re;
-  xv[1] = im;
+  T* xv = x + ((I * nm + m) * 4 + f) * 2;
+  xv[0] = (T)re;
+  xv[1] = (T)im;
 }
 
 // Samples -> modes: b[a][m][f] = (1/N) sum_s q[a][f][s] e^{-2 pi i m s / N}
 // (m = 0..K), one lane per (node, mode); q has in_ch channels per node.
-template <typename TQ>
+template <typename TQ, typename T>
 __global__ void __launch_bounds__(PBLK)
 k_pc_to_modes(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
-              const double* __restrict__ cs, double* __restrict__ b) {
+              const double* __restrict__ cs, T* __restrict__ b) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= n * nm) return;
   const int64_t a = gid / nm;
   const int m = (int)(gid - a * nm);
-  cplx out[4];
+  cplxT<T> out[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     double re = 0.0, im = 0.0;
@@ -587,16 +615,16 @@ k_pc_to_modes(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
       re += v * cs[(m * N + s) * 2];
       im -= v * cs[(m * N + s) * 2 + 1];
     }
-    out[f] = {re / N, im / N};
+    out[f] = {(T)(re / N), (T)(im / N)};
   }
   store4(b, gid, out);
 }
 
 // Modes -> samples: z[a][f][s] = Re x_0 + 2 sum_{m>=1} Re(x_m e^{2 pi i m s/N}),
 // one lane per (node, field, sample).
-template <typename TZ>
+template <typename T, typename TZ>
 __global__ void __launch_bounds__(PBLK)
-k_pc_from_modes(int64_t n, int N, int nm, const double* __restrict__ x,
+k_pc_from_modes(int64_t n, int N, int nm, const T* __restrict__ x,
                 const double* __restrict__ cs, TZ* __restrict__ z) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= n * 4 * N) return;
@@ -604,10 +632,10 @@ k_pc_from_modes(int64_t n, int N, int nm, const double* __restrict__ x,
   const int r = (int)(gid - a * 4 * N);
   const int f = r / N;
   const int s = r - f * N;
-  double v = x[((a * nm + 0) * 4 + f) * 2];
+  double v = (double)x[((a * nm + 0) * 4 + f) * 2];
   for (int m = 1; m < nm; ++m) {
-    const double* xm = x + ((a * nm + m) * 4 + f) * 2;
-    v += 2.0 * (xm[0] * cs[(m * N + s) * 2] - xm[1] * cs[(m * N + s) * 2 + 1]);
+    const T* xm = x + ((a * nm + m) * 4 + f) * 2;
+    v += 2.0 * ((double)xm[0] * cs[(m * N + s) * 2] - (double)xm[1] * cs[(m * N + s) * 2 + 1]);
   }
   z[gid] = (TZ)v;
 }
@@ -626,6 +654,8 @@ struct PcLevel {
   // coarse node, and the fine entries of each coarse entry
   DeviceArray<int32_t> agg, mptr, mem, gptr, gsrc;
   DeviceArray<double> x, x2, b, r;
+  // FP32 copies of the coefficients and vectors for FP32 cycles
+  DeviceArray<float> valf, xf, x2f, bf, rf;
   // colour classes of the level's graph (Gauss-Seidel smoothing)
   DeviceArray<int32_t> crows;
   std::vector<int64_t> cptr;
@@ -645,13 +675,15 @@ struct Precond {
   double gamma = 1.0;  // weight of the coarse-level correction
   int smoother = 0;    // 0 damped block Jacobi, 1 symmetric block Gauss-Seidel
   int wcycle = 0;      // 1: two coarse-level cycles per level (W-cycle)
+  int fp32 = 0;        // 1: cycles on FP32 vectors and coefficients
   Coef coef{};
   size_t bytes() const {
     size_t b = cs.bytes() + dense.bytes() + work.bytes() + inv.bytes();
     for (const auto& l : lv)
       b += l.rowptr.bytes() + l.col.bytes() + l.diag.bytes() + l.val.bytes() + l.agg.bytes() +
            l.mptr.bytes() + l.mem.bytes() + l.gptr.bytes() + l.gsrc.bytes() + l.x.bytes() +
-           l.x2.bytes() + l.b.bytes() + l.r.bytes();
+           l.x2.bytes() + l.b.bytes() + l.r.bytes() + l.valf.bytes() + l.xf.bytes() +
+           l.x2f.bytes() + l.bf.bytes() + l.rf.bytes();
     return b;
   }
 };
@@ -901,10 +933,17 @@ hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int co
 namespace {
 
 // Vectors and trigonometric table for K + 1 modes.
-hipError_t ensure_modes(Precond* pc, int N) {
+hipError_t ensure_modes(Precond* pc, int N, int fp32) {
   const int nm = (N - 1) / 2 + 1;
-  if (pc->nm == nm && pc->N == N) return hipSuccess;
   hipError_t e;
+  if (fp32)
+    for (auto& L : pc->lv) {
+      const size_t len = (size_t)L.n * nm * 8;
+      if ((e = L.valf.ensure((size_t)L.nnz * PC_NF)) || (e = L.xf.ensure(len)) ||
+          (e = L.x2f.ensure(len)) || (e = L.bf.ensure(len)) || (e = L.rf.ensure(len)))
+        return e;
+    }
+  if (pc->nm == nm && pc->N == N) return hipSuccess;
   for (auto& L : pc->lv) {
     const size_t len = (size_t)L.n * nm * 8;
     if ((e = L.x.ensure(len)) || (e = L.x2.ensure(len)) || (e = L.b.ensure(len)) ||
@@ -933,9 +972,10 @@ hipError_t ensure_modes(Precond* pc, int N) {
 
 hipError_t precond_setup(Precond* pc, const DevMesh& m, const Phys& p, const double* Sy,
                          double sigma, int nu, int cycles, double wj, double gamma, int smoother,
-                         int wcycle, hipStream_t st) {
-  hipError_t e = ensure_modes(pc, p.N);
+                         int wcycle, int fp32, hipStream_t st) {
+  hipError_t e = ensure_modes(pc, p.N, fp32);
   if (e != hipSuccess) return e;
+  pc->fp32 = fp32;
   pc->smoother = smoother;
   pc->wcycle = wcycle;
   pc->nu = nu;
@@ -955,6 +995,11 @@ hipError_t precond_setup(Precond* pc, const DevMesh& m, const Phys& p, const dou
     hipLaunchKernelGGL(k_pc_galerkin, dim3(nblk(B.nnz * PC_NFIELDS)), dim3(PBLK), 0, st, B.nnz,
                        A.gptr.p, A.gsrc.p, A.val.p, B.val.p);
   }
+  if (fp32)
+    for (auto& L : pc->lv) {
+      const int64_t len = L.nnz * PC_NF;
+      hipLaunchKernelGGL(k_pc_narrow, dim3(nblk(len)), dim3(PBLK), 0, st, len, L.val.p, L.valf.p);
+    }
   PcLevel& C = pc->lv.back();
   const int64_t D = pc->dense_D;
   if ((e = hipMemsetAsync(pc->dense.p, 0, pc->dense.bytes(), st))) return e;
@@ -968,50 +1013,88 @@ hipError_t precond_setup(Precond* pc, const DevMesh& m, const Phys& p, const dou
 
 namespace {
 
+// The level's vectors and coefficients in the cycle's precision.
+template <typename T>
+struct LevelVecs;
+template <>
+struct LevelVecs<double> {
+  static double*& x(PcLevel& L) { return L.x.p; }
+  static double*& x2(PcLevel& L) { return L.x2.p; }
+  static double* b(PcLevel& L) { return L.b.p; }
+  static double* r(PcLevel& L) { return L.r.p; }
+  static const double* val(PcLevel& L) { return L.val.p; }
+};
+template <>
+struct LevelVecs<float> {
+  static float*& x(PcLevel& L) { return L.xf.p; }
+  static float*& x2(PcLevel& L) { return L.x2f.p; }
+  static float* b(PcLevel& L) { return L.bf.p; }
+  static float* r(PcLevel& L) { return L.rf.p; }
+  static const float* val(PcLevel& L) { return L.valf.p; }
+};
+
+template <typename T>
 hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
+  using V = LevelVecs<T>;
   PcLevel& L = pc->lv[l];
   const int nm = pc->nm;
   if (l + 1 == pc->lv.size()) {
-    hipLaunchKernelGGL(k_pc_dense_apply, dim3(nblk(4 * L.n * nm)), dim3(PBLK), 0, st, L.n, nm,
-                       pc->inv.p, L.b.p, L.x.p);
+    hipLaunchKernelGGL(k_pc_dense_apply<T>, dim3(nblk(4 * L.n * nm)), dim3(PBLK), 0, st, L.n, nm,
+                       pc->inv.p, V::b(L), V::x(L));
     return hipGetLastError();
   }
   const unsigned g = nblk(L.n * nm);
   auto sweep = [&](bool from_zero, bool reverse) {
     if (pc->smoother == 1) {
       if (from_zero)
-        hipLaunchKernelGGL(k_pc_zero, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st,
-                           L.n * nm * 8, L.x.p);
+        hipLaunchKernelGGL(k_pc_zero<T>, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st,
+                           L.n * nm * 8, V::x(L));
       const int nc = (int)L.cptr.size() - 1;
       for (int q = 0; q < nc; ++q) {
         const int c = reverse ? nc - 1 - q : q;
         const int64_t nr = L.cptr[c + 1] - L.cptr[c];
-        hipLaunchKernelGGL(k_pc_gs, dim3(nblk(nr * nm)), dim3(PBLK), 0, st, nr,
-                           L.crows.p + L.cptr[c], L.rowptr.p, L.col.p, L.diag.p, L.val.p,
-                           pc->coef, L.b.p, L.x.p);
+        hipLaunchKernelGGL((k_pc_gs<T, T>), dim3(nblk(nr * nm)), dim3(PBLK), 0, st, nr,
+                           L.crows.p + L.cptr[c], L.rowptr.p, L.col.p, L.diag.p, V::val(L),
+                           pc->coef, V::b(L), V::x(L));
       }
       return;
     }
-    hipLaunchKernelGGL(k_pc_rows<2>, dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
-                       L.diag.p, L.val.p, pc->coef, L.b.p, from_zero ? nullptr : L.x.p, L.x2.p,
-                       pc->wj);
-    std::swap(L.x.p, L.x2.p);
+    hipLaunchKernelGGL((k_pc_rows<2, T, T>), dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
+                       L.diag.p, V::val(L), pc->coef, V::b(L), from_zero ? nullptr : V::x(L),
+                       V::x2(L), pc->wj);
+    std::swap(V::x(L), V::x2(L));
   };
   for (int k = 0; k < pc->nu; ++k) sweep(zero_start && k == 0, false);
-  hipLaunchKernelGGL(k_pc_rows<1>, dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
-                     L.diag.p, L.val.p, pc->coef, L.b.p, L.x.p, L.r.p, 0.0);
+  hipLaunchKernelGGL((k_pc_rows<1, T, T>), dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
+                     L.diag.p, V::val(L), pc->coef, V::b(L), V::x(L), V::r(L), 0.0);
   PcLevel& C = pc->lv[l + 1];
-  hipLaunchKernelGGL(k_pc_restrict, dim3(nblk(C.n * nm * 8)), dim3(PBLK), 0, st, C.n, nm,
-                     L.mptr.p, L.mem.p, L.r.p, C.b.p);
-  hipError_t e = vcycle(pc, l + 1, true, st);
+  hipLaunchKernelGGL(k_pc_restrict<T>, dim3(nblk(C.n * nm * 8)), dim3(PBLK), 0, st, C.n, nm,
+                     L.mptr.p, L.mem.p, V::r(L), V::b(C));
+  hipError_t e = vcycle<T>(pc, l + 1, true, st);
   if (e != hipSuccess) return e;
   if (pc->wcycle && l + 2 < pc->lv.size()) {
-    e = vcycle(pc, l + 1, false, st);
+    e = vcycle<T>(pc, l + 1, false, st);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_pc_prolong, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st, L.n, nm, L.agg.p,
-                     C.x.p, L.x.p, pc->gamma);
+  hipLaunchKernelGGL(k_pc_prolong<T>, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st, L.n, nm,
+                     L.agg.p, V::x(C), V::x(L), pc->gamma);
   for (int k = 0; k < pc->nu; ++k) sweep(false, true);
+  return hipGetLastError();
+}
+
+template <typename T, typename TQ, typename TZ>
+hipError_t apply_in(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st) {
+  using V = LevelVecs<T>;
+  const int nm = pc->nm, N = pc->N;
+  PcLevel& F = pc->lv[0];
+  hipLaunchKernelGGL((k_pc_to_modes<TQ, T>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm, q,
+                     in_ch, pc->cs.p, V::b(F));
+  for (int c = 0; c < pc->cycles; ++c) {
+    hipError_t e = vcycle<T>(pc, 0, c == 0, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_pc_from_modes<T, TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n, N, nm,
+                     V::x(F), pc->cs.p, z);
   return hipGetLastError();
 }
 
@@ -1019,29 +1102,20 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
 
 template <typename TQ, typename TZ>
 hipError_t precond_apply(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st) {
-  const int nm = pc->nm, N = pc->N;
-  PcLevel& F = pc->lv[0];
-  hipLaunchKernelGGL((k_pc_to_modes<TQ>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm, q,
-                     in_ch, pc->cs.p, F.b.p);
-  for (int c = 0; c < pc->cycles; ++c) {
-    hipError_t e = vcycle(pc, 0, c == 0, st);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((k_pc_from_modes<TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n, N, nm,
-                     F.x.p, pc->cs.p, z);
-  return hipGetLastError();
+  return pc->fp32 ? apply_in<float>(pc, n, q, in_ch, z, st)
+                  : apply_in<double>(pc, n, q, in_ch, z, st);
 }
 
 template <typename TQ, typename TZ>
 hipError_t precond_matvec(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st) {
   const int nm = pc->nm, N = pc->N;
   PcLevel& F = pc->lv[0];
-  hipLaunchKernelGGL((k_pc_to_modes<TQ>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm, q,
-                     in_ch, pc->cs.p, F.b.p);
-  hipLaunchKernelGGL(k_pc_rows<0>, dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, F.rowptr.p, F.col.p,
-                     F.diag.p, F.val.p, pc->coef, nullptr, F.b.p, F.x.p, 0.0);
-  hipLaunchKernelGGL((k_pc_from_modes<TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n, N, nm,
-                     F.x.p, pc->cs.p, z);
+  hipLaunchKernelGGL((k_pc_to_modes<TQ, double>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm,
+                     q, in_ch, pc->cs.p, F.b.p);
+  hipLaunchKernelGGL((k_pc_rows<0, double, double>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n,
+                     F.rowptr.p, F.col.p, F.diag.p, F.val.p, pc->coef, nullptr, F.b.p, F.x.p, 0.0);
+  hipLaunchKernelGGL((k_pc_from_modes<double, TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n,
+                     N, nm, F.x.p, pc->cs.p, z);
   return hipGetLastError();
 }
 

@@ -307,7 +307,8 @@ def test_reduced_tjunction_solve_matches_oracle(precision):
     start to 1e-12 of the initial residual (mean-flow multigrid) reaches the
     oracle's stored root (modal values at 2,048 seeded nodes, 1e-10), and
     the oracle's residual at the GPU solution is below 1e-8 of the oracle's
-    initial residual (the certificate)."""
+    initial residual (the certificate).  The mixed solve also runs the
+    multigrid cycles in FP32."""
     path = os.path.join(HERE, "golden", "c2_reduced_solution.npz")
     if not os.path.exists(path):
         pytest.skip("stored oracle root not written (tests/golden/make_golden.py c2)")
@@ -328,7 +329,7 @@ def test_reduced_tjunction_solve_matches_oracle(precision):
     rep = hbl.newton_solve(c.gm, P.params, c.bc, Y,
                            hbl.SolveOptions(rtol=1e-12, max_newton=200, max_gmres=1000,
                                             precond=hbl.HB_PREC_MEANFLOW, amg_cycles=2,
-                                            precision=prec))
+                                            precision=prec, amg_fp32=int(precision == "mixed")))
     print(precision, {k: rep[k] for k in ("newton_iters", "gmres_iters", "r0", "r_final",
                                           "wall_s", "mass_defect")}, flush=True)
     assert rep["status"] == 0

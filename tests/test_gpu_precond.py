@@ -111,17 +111,36 @@ def test_meanflow_multilevel_hierarchy(c1):
     assert np.all(np.isfinite(res))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["c1", "tj"])
+def test_fp32_cycle_matches_fp64_cycle(case, request):
+    """The FP32 cycle (amg_fp32) is the FP64 cycle up to FP32 rounding: the
+    same linear map, applied with 24-bit mantissas in the smoothing, residual
+    and transfer steps; relative difference <= 1e-4 (a few hundred roundings
+    of 6e-8 through a cycle whose amplification is O(10))."""
+    c = request.getfixturevalue(case)
+    Y, X = seeded_state(c.P, 36), seeded_state(c.P, 37)
+    X[:3][:, :, c.om.dirichlet] = 0.0
+    out = {}
+    for fp32 in (0, 1):
+        out[fp32] = host(hbl.precond_apply(c.gm, c.P.params, c.bc, dev(Y), dev(X), 5.0,
+                                           op="inverse", cycles=2, coarse_max=24, fp32=fp32))
+    d = rel(out[1], out[0])
+    print(case, "fp32 vs fp64 cycle", d, flush=True)
+    assert np.all(np.isfinite(out[1])) and d <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed-fp32cycle"])
 def test_solve_meanflow_matches_oracle_solution(c1, precision):
     g = np.load(os.path.join(HERE, "golden", "c1_solution.npz"))
     P = c1.P
-    prec = hbl.HB_MIXED if precision == "mixed" else hbl.HB_F64
+    prec = hbl.HB_F64 if precision == "fp64" else hbl.HB_MIXED
     reps = {}
     for pc in (hbl.HB_PREC_NODE_TIME, hbl.HB_PREC_MEANFLOW):
         Y = dev(g["Y0"])
         reps[pc] = hbl.newton_solve(c1.gm, P.params, c1.bc, Y,
                                     hbl.SolveOptions(rtol=1e-12, max_newton=400, max_gmres=1000,
-                                                     precision=prec, precond=pc))
+                                                     precision=prec, precond=pc,
+                                                     amg_fp32=int(precision.endswith("cycle"))))
         assert reps[pc]["status"] == 0
         assert rel(host(Y), g["Y"]) <= TOL
     print(precision, {k: (v["newton_iters"], v["gmres_iters"], round(v["wall_s"], 3))
