@@ -432,6 +432,33 @@ int hb_mlp_adam_step(hb_mlp* net, const float* grad, float lr, void* stream);
 int hb_pod_expand(int64_t L, int32_t r, const double* base, const double* mean,
                   const double* basis, const float* coef, double* Y, void* stream);
 
+/* Proper orthogonal decomposition of a snapshot set by the method of
+ * snapshots, for the network's targets.  Snapshot i is row i of S minus row
+ * i of B (device [ns][L] FP64 row-major; B NULL for none; both read only).
+ * With c_i = snapshot i - mean and the Gram matrix G_ij = c_i . c_j =
+ * sum_k V_ik lam_k V_jk (lam descending), the modes are
+ * basis_k = sum_i V_ik c_i / sqrt(lam_k) (orthonormal) for k < r, where r
+ * counts the leading lam_k > max(0, floor_rel lam_0) among the first r_max.
+ * Outputs: mean (device [L]); basis (device [r_max][L], rows >= r left as
+ * they are); coef (host [ns][r_max]) = V_ik sqrt(lam_k) = c_i . basis_k,
+ * zero for k >= r; lam (host [ns]) every eigenvalue of G, descending;
+ * *r_out = r.  Mean, Gram matrix (FP64 atomics, so not bitwise
+ * reproducible) and modes run on the device; the ns x ns eigenproblem on
+ * the host (hb_sym_eig).  Needs 1 <= ns <= 4096, 1 <= r_max <= ns; device
+ * scratch of ns (ns + r) doubles is allocated per call.  Waits for the
+ * stream.  HB_ERR_NAN for a non-finite Gram matrix. */
+int hb_pod_fit(const double* S, const double* B, int64_t ns, int64_t L, int32_t r_max,
+               double floor_rel, double* mean, double* basis, double* coef, double* lam,
+               int32_t* r_out, void* stream);
+/* Host symmetric eigenproblem (no device work): A (host [n][n] row-major,
+ * exactly symmetric, read only) = V diag(w) V^T with w (host [n])
+ * descending and V (host [n][n] row-major) orthogonal, column k the
+ * eigenvector of w[k].  Householder tridiagonalisation, then implicit QR
+ * steps with Wilkinson shifts (Golub and Van Loan, ch. 8).  1 <= n <= 4096.
+ * HB_ERR_ARG for a non-finite or non-symmetric A; HB_ERR_NOCONV if 30 n QR
+ * steps do not converge. */
+int hb_sym_eig(int32_t n, const double* A, double* w, double* V);
+
 const char* hb_last_error(void);
 
 #ifdef __cplusplus

@@ -122,6 +122,8 @@ def load():
     lib.hb_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, C.POINTER(C.c_double), vp]
     lib.hb_mlp_adam_step.argtypes = [vp, vp, C.c_float, vp]
     lib.hb_pod_expand.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp]
+    lib.hb_pod_fit.argtypes = [vp, vp, i64, i64, i32, dbl, vp, vp, vp, vp, C.POINTER(i32), vp]
+    lib.hb_sym_eig.argtypes = [i32, vp, vp, vp]
     lib.hb_precond_apply.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, dbl,
                                      C.POINTER(_PcOpts), i32, vp, vp, vp]
     lib.hb_precond_levels.argtypes = [vp, vp, i32, C.POINTER(i32)]
@@ -131,7 +133,8 @@ def load():
                  "hb_newton_solve", "hb_set_timing", "hb_last_timings", "hb_mlp_create",
                  "hb_mlp_num_params", "hb_mlp_get_params", "hb_mlp_forward",
                  "hb_mlp_forward_noalloc", "hb_mlp_loss_grad",
-                 "hb_mlp_adam_step", "hb_pod_expand", "hb_tm_residual", "hb_tm_jvp",
+                 "hb_mlp_adam_step", "hb_pod_expand", "hb_pod_fit", "hb_sym_eig",
+                 "hb_tm_residual", "hb_tm_jvp",
                  "hb_tm_march", "hb_precond_apply", "hb_precond_levels", "hb_outlet_flow"):
         getattr(lib, name).restype = C.c_int
     _lib = lib

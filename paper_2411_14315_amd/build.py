@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhb.so")
-SOURCES = ["hb_kernels.hip", "hb_host.cpp", "hb_mlp.hip", "hb_precond.hip"]
+SOURCES = ["hb_kernels.hip", "hb_host.cpp", "hb_mlp.hip", "hb_precond.hip", "hb_pod.hip"]
 
 
 def hipcc() -> str:

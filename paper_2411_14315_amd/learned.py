@@ -6,10 +6,11 @@ initial guess only if its FP64 residual is below that of the plain steady
 start; otherwise the plain start is kept, and the final FP64 residual decides
 convergence either way.
 
-Only argument marshalling and small host-side statistics happen here
-(standardisation, the n x n eigenproblem of the method of snapshots); the
-snapshot Gram matrix and the projections are device GEMMs, and every network
-step runs in the library's kernels.
+Only argument marshalling and small host-side statistics (standardisation
+of the parameters and coefficients) happen here: the POD (hb_pod_fit: mean,
+Gram matrix and modes on the device, the small eigenproblem in the library's
+host code), every network step and the expansion of the guess run in the
+library.
 """
 from __future__ import annotations
 
@@ -19,8 +20,8 @@ from dataclasses import dataclass, replace
 
 import numpy as np
 
-from . import (BC, HB_F64, Mesh, SolveOptions, _arg, _check, _stream, load, newton_solve,
-               residual)
+from . import (BC, HB_F64, HB_PREC_MEANFLOW, Mesh, SolveOptions, _arg, _check, _stream, load,
+               newton_solve, residual)
 
 
 class MLP:
@@ -116,10 +117,43 @@ def pod_expand(mean, basis, coef, Y, base=None, stream=None):
     return Y
 
 
+def pod_fit(S, rank: int, base=None, floor_rel: float = 1e-14, stream=None):
+    """POD of the rows of S (minus the rows of base): returns (mean (L,),
+    basis (r, L) orthonormal rows, coef (ns, r) host, lam (ns,) host, r)
+    with r <= rank modes (see hb_pod_fit)."""
+    import torch
+    ns, L = int(S.shape[0]), int(S.shape[1])
+    sp = _arg(S, "S", (ns, L))
+    bp = None if base is None else _arg(base, "base", (ns, L), device=S.device)
+    mean = torch.empty(L, dtype=torch.float64, device=S.device)
+    basis = torch.empty((int(rank), L), dtype=torch.float64, device=S.device)
+    coef = np.zeros((ns, int(rank)))
+    lam = np.zeros(ns)
+    r = C.c_int32()
+    _check(load().hb_pod_fit(sp, bp, ns, L, int(rank), float(floor_rel), mean.data_ptr(),
+                             basis.data_ptr(), coef.ctypes.data, lam.ctypes.data, C.byref(r),
+                             _stream(stream)))
+    r = int(r.value)
+    return mean, basis[:r], np.ascontiguousarray(coef[:, :r]), lam, r
+
+
+def sym_eig(A: np.ndarray):
+    """Host symmetric eigenproblem (hb_sym_eig): w descending, V columns."""
+    A = np.ascontiguousarray(A, np.float64)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("A must be square")
+    w, V = np.zeros(n), np.zeros((n, n))
+    _check(load().hb_sym_eig(n, A.ctypes.data, w.ctypes.data, V.ctypes.data))
+    return w, V
+
+
 def sample_norm(R, K: int) -> float:
-    """2-norm over time samples of modal rows (Parseval for the real DFT)."""
+    """2-norm over time samples of modal rows (Parseval for the real DFT),
+    on a host copy."""
     N = 2 * K + 1
-    R = R.reshape(-1, N, R.shape[-1]) if R.dim() == 3 else R
+    R = R.cpu().numpy()
+    R = R.reshape(-1, N, R.shape[-1]) if R.ndim == 3 else R
     return float(N * ((R[:, 0] ** 2).sum() + 0.5 * (R[:, 1:] ** 2).sum())) ** 0.5
 
 
@@ -151,7 +185,8 @@ class Case:
         dev = self.bc.dirichlet.device
         Ys = torch.zeros((4, 1, n), dtype=torch.float64, device=dev)
         newton_solve(self.mesh, replace(self.params, K=0), self.bc0, Ys,
-                     SolveOptions(rtol=rtol, max_newton=100, max_gmres=500),
+                     SolveOptions(rtol=rtol, max_newton=100, max_gmres=500,
+                                  precond=HB_PREC_MEANFLOW, amg_cycles=2),
                      raise_on_noconv=False)
         Y = torch.zeros((4, self.params.N, n), dtype=torch.float64, device=dev)
         Y[:, 0] = Ys[:, 0]
@@ -160,28 +195,38 @@ class Case:
     def residual_norm(self, Y) -> float:
         return sample_norm(residual(self.mesh, self.params, self.bc, Y), self.params.K)
 
-    def solve(self, Y, r_ref: float, rtol=1e-8, max_newton=300, precision=HB_F64, cfl=1.0):
+    def solve(self, Y, r_ref: float, rtol=1e-8, max_newton=300, precision=HB_F64, cfl=1.0,
+              verbose=0):
         import torch
         torch.cuda.synchronize()
         t = time.perf_counter()
         rep = newton_solve(self.mesh, self.params, self.bc, Y,
                            SolveOptions(rtol=rtol, r_ref=r_ref, max_newton=max_newton,
-                                        max_gmres=500, precision=precision, cfl=cfl),
+                                        max_gmres=500, precision=precision, cfl=cfl,
+                                        precond=HB_PREC_MEANFLOW, amg_cycles=2,
+                                        amg_fp32=int(precision != HB_F64), verbose=verbose),
                            raise_on_noconv=False)
         torch.cuda.synchronize()
         rep["wall_s"] = time.perf_counter() - t
         return rep
 
 
-def generate_snapshots(problems, batch: int = 64, rtol=1e-9, device="cuda:0"):
-    """Solve every problem (same topology) with the method itself, `batch`
-    at a time as one disjoint-union mesh, from the plain start.  Returns the
-    (n_problems, 4 N n) FP64 device matrices of the solutions and of the
-    plain starts, and statistics."""
+def generate_snapshots(problems, batch: int = 1, rtol=1e-9, device="cuda:0", precision=HB_F64,
+                       log=None, max_newton=400, verbose=0):
+    """Solve every problem (same topology) with the method itself, from the
+    plain start, to the FP64 residual rtol ||r(plain start)||; `batch`
+    problems at a time as one disjoint-union mesh (worth it only for meshes
+    too small to fill the GPU: GMRES on the union converges as on its
+    hardest member, or slower).  `precision` is the Krylov precision
+    (HB_MIXED: FP32 Jv, basis and multigrid cycles).  Returns the
+    (n_kept, 4 N n) FP64 device matrices of the solutions and of the plain
+    starts, and statistics; with batch = 1 a draw whose solve does not
+    converge within max_newton steps is left out (its index is not in
+    stats["kept"]).  verbose = 1 prints every Newton step (stderr)."""
     import torch
     from hbinputs.problems import stack
     sols, starts = [], []
-    stats = dict(solves=0, newton=0, gmres=0, unconverged=0)
+    stats = dict(solves=0, newton=0, gmres=0, unconverged=0, kept=[])
     t0 = time.perf_counter()
 
     def rows(Y, g, n):
@@ -189,17 +234,25 @@ def generate_snapshots(problems, batch: int = 64, rtol=1e-9, device="cuda:0"):
 
     for i in range(0, len(problems), batch):
         group = problems[i:i + batch]
-        c = Case.build(stack(group), device)
+        c = Case.build(group[0] if len(group) == 1 else stack(group), device)
         Y = c.plain_start()
         n = group[0].mesh.n_nodes
-        starts.append(rows(Y, len(group), n))
-        rep = c.solve(Y, r_ref=0.0, rtol=rtol, max_newton=400)
+        Ys = rows(Y, len(group), n).clone()
+        rep = c.solve(Y, r_ref=0.0, rtol=rtol, max_newton=max_newton, precision=precision,
+                      verbose=verbose)
         stats["solves"] += 1
         stats["newton"] += rep["newton_iters"]
         stats["gmres"] += rep["gmres_iters"]
         stats["unconverged"] += int(rep["status"] != 0)
-        sols.append(rows(Y, len(group), n))
+        if rep["status"] == 0 or len(group) > 1:
+            starts.append(Ys)
+            sols.append(rows(Y, len(group), n))
+            stats["kept"].extend(range(i, i + len(group)))
         c.mesh.close()
+        if log is not None:
+            log(f"snapshots {i + len(group)}/{len(problems)}: newton {rep['newton_iters']} "
+                f"gmres {rep['gmres_iters']} status {rep['status']} "
+                f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     stats["wall_s"] = time.perf_counter() - t0
     return torch.cat(sols).contiguous(), torch.cat(starts).contiguous(), stats
@@ -228,22 +281,11 @@ class WarmStart:
         plain starts (required for the correction target)."""
         import torch
         t = time.perf_counter()
-        if self.target == "correction":
-            if Y0 is None:
-                raise ValueError("the correction target needs the plain starts")
-            Y = Y - Y0
-        self.mean = Y.mean(dim=0).contiguous()
-        S = Y - self.mean
-        G = (S @ S.T).cpu().numpy()                     # method of snapshots: n x n Gram
-        lam, V = np.linalg.eigh(G)
-        order = np.argsort(lam)[::-1][: self.rank]
-        lam, V = lam[order], V[:, order]
-        keep = lam > lam[0] * 1e-14
-        lam, V = lam[keep], V[:, keep]
-        self.energy = float(lam.sum() / max(np.trace(G), 1e-300))
-        Vd = torch.from_numpy(np.ascontiguousarray(V / np.sqrt(lam))).to(Y.device)
-        self.basis = (Vd.T @ S).contiguous()             # (r, L) orthonormal rows
-        coef = (S @ self.basis.T).cpu().numpy()          # (n, r)
+        if self.target == "correction" and Y0 is None:
+            raise ValueError("the correction target needs the plain starts")
+        base = Y0 if self.target == "correction" else None
+        self.mean, self.basis, coef, lam, _ = pod_fit(Y, self.rank, base=base)
+        self.energy = float(lam[:self.basis.shape[0]].sum() / max(lam[lam > 0].sum(), 1e-300))
         self.r = int(self.basis.shape[0])
         self.x_mu, self.x_sd = thetas.mean(0), thetas.std(0) + 1e-12
         # one scale for every coefficient, so that the loss measures the
@@ -270,9 +312,8 @@ class WarmStart:
         if self.target == "correction" and plain is None:
             raise ValueError("the correction target needs the plain start")
         x = ((np.atleast_2d(theta) - self.x_mu) / self.x_sd).astype(np.float32)
-        c = self.net.forward(torch.from_numpy(x).to(self.mean.device))
-        cd = (c[0] * torch.from_numpy(self.c_sd.astype(np.float32)).to(c.device)
-              + torch.from_numpy(self.c_mu.astype(np.float32)).to(c.device)).contiguous()
+        c = self.net.forward(torch.from_numpy(x).to(self.mean.device)).cpu().numpy()[0]
+        cd = torch.from_numpy((c * self.c_sd + self.c_mu).astype(np.float32)).to(self.mean.device)
         Y = torch.empty(shape, dtype=torch.float64, device=self.mean.device)
         base = plain.reshape(-1) if self.target == "correction" else None
         pod_expand(self.mean, self.basis, cd, Y.view(-1), base=base)
@@ -280,7 +321,7 @@ class WarmStart:
 
 
 def compare_starts(model: WarmStart, case: Case, theta, rtol=1e-8, learned_max_newton=60,
-                   precision=HB_F64):
+                   precision=HB_F64, verbose=0):
     """Plain start vs learned guess, both to the same absolute FP64 residual
     rtol * ||r(plain start)|| with the given Krylov precision.  If Newton from
     the guess does not converge within learned_max_newton steps (or breaks
@@ -303,7 +344,7 @@ def compare_starts(model: WarmStart, case: Case, theta, rtol=1e-8, learned_max_n
     t0 = time.perf_counter()
     try:
         rep_l = case.solve(Yl, r_plain, rtol, max_newton=learned_max_newton,
-                           precision=precision)
+                           precision=precision, verbose=verbose)
     except HBError as e:         # non-finite residual on the way
         torch.cuda.synchronize()
         rep_l = dict(status=e.status, newton_iters=learned_max_newton, gmres_iters=0,
@@ -311,17 +352,18 @@ def compare_starts(model: WarmStart, case: Case, theta, rtol=1e-8, learned_max_n
     used = "learned"
     if rep_l["status"] != 0:
         Yl = Yp.clone()
-        rep_f = case.solve(Yl, r_plain, rtol, precision=precision)
+        rep_f = case.solve(Yl, r_plain, rtol, precision=precision, verbose=verbose)
         rep_l = dict(rep_f, newton_iters=rep_l["newton_iters"] + rep_f["newton_iters"],
                      gmres_iters=rep_l["gmres_iters"] + rep_f["gmres_iters"],
                      wall_s=rep_l["wall_s"] + rep_f["wall_s"])
         used = "plain"
     Y0 = Yp.clone()
-    rep_p = case.solve(Yp, r_plain, rtol, precision=precision)
-    nrm = torch.linalg.norm(Yp)
+    rep_p = case.solve(Yp, r_plain, rtol, precision=precision, verbose=verbose)
+    root = Yp.cpu().numpy()
+    nrm = np.linalg.norm(root)
 
     def err(Y):
-        return float((torch.linalg.norm(Y - Yp) / nrm).item())
+        return float(np.linalg.norm(Y.cpu().numpy() - root) / nrm)
 
     return {"plain": dict(rep_p, start_s=t_plain, r_start=r_plain, start_err=err(Y0)),
             "learned": dict(rep_l, start_s=t_guess, r_start=r_guess, start_err=err(Yg),

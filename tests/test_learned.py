@@ -82,6 +82,36 @@ def _bf16(x):
     return (u.astype(np.uint32) << 16).view(np.float32)
 
 
+def test_host_symmetric_eigensolver():
+    """hb_sym_eig (host code, no device work) against LAPACK's eigvalsh and
+    the defining identities A V = V diag(w), V^T V = I, on random matrices,
+    repeated eigenvalues, a rank-2 Gram matrix, block-diagonal (deflating)
+    and 1 x 1 cases; bad input is rejected."""
+    import paper_2411_14315_amd as hbl
+    from paper_2411_14315_amd.learned import sym_eig
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(30, 2))
+    blocks = np.zeros((9, 9))
+    blocks[:4, :4] = np.ones((4, 4))
+    blocks[4:, 4:] = np.diag([5.0, -1.0, 2.0, 2.0, 0.0])
+    cases = [rng.normal(size=(n, n)) for n in (1, 2, 3, 17, 64, 129)]
+    cases = [A + A.T for A in cases] + [np.diag([3.0, 1, 3, 1, 2, 2, 2]), np.eye(5), X @ X.T,
+                                        blocks]
+    for A in cases:
+        A = 0.5 * (A + A.T)
+        n = A.shape[0]
+        w, V = sym_eig(A)
+        scale = max(np.linalg.norm(A, 2), 1e-300)
+        assert np.all(np.diff(w) <= 0)
+        assert np.abs(w - np.sort(np.linalg.eigvalsh(A))[::-1]).max() <= 1e-13 * scale * n
+        assert np.linalg.norm(A @ V - V * w) <= 1e-13 * scale * n
+        assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-13 * n
+    with pytest.raises(hbl.HBError):
+        sym_eig(np.array([[1.0, 2.0], [2.5, 1.0]]))            # not symmetric
+    with pytest.raises(hbl.HBError):
+        sym_eig(np.array([[np.nan, 0.0], [0.0, 1.0]]))
+
+
 @pytest.fixture(scope="module")
 def torch_gpu():
     torch = pytest.importorskip("torch")
@@ -198,6 +228,37 @@ def test_pod_expand_parity(torch_gpu):
     pod_expand(torch.from_numpy(mean).cuda(), torch.from_numpy(basis).cuda(),
                torch.from_numpy(coef).cuda(), B, base=B)       # in place on the base
     assert np.linalg.norm(B.cpu().numpy() - base - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+@pytest.mark.gpu
+def test_pod_fit_against_svd(torch_gpu):
+    """hb_pod_fit on 150 snapshots (three 64-row Gram tiles, the last ragged)
+    of length 10,007 with a base subtracted: mean, eigenvalues, modes and
+    coefficients against numpy's SVD of the centred snapshots (distinct
+    singular values, so each mode is fixed up to sign)."""
+    torch = torch_gpu
+    from paper_2411_14315_amd.learned import pod_fit
+    rng = np.random.default_rng(6)
+    ns, L, r = 150, 10007, 20
+    U = np.linalg.qr(rng.normal(size=(L, 40)))[0]
+    sv = 10.0 ** -np.linspace(0, 4, 40)
+    S = rng.normal(size=(ns, 40)) * sv @ U.T + 3.0
+    B = rng.normal(size=(ns, L))
+    mean, basis, coef, lam, rr = pod_fit(torch.from_numpy(S + B).cuda(), r,
+                                         base=torch.from_numpy(B).cuda())
+    Sc = S - S.mean(0)
+    u, s, vt = np.linalg.svd(Sc, full_matrices=False)
+    assert rr == r and basis.shape == (r, L) and coef.shape == (ns, r)
+    m, Bm = mean.cpu().numpy(), basis.cpu().numpy()
+    assert np.linalg.norm(m - S.mean(0)) <= 1e-13 * np.linalg.norm(S.mean(0))
+    assert np.allclose(lam[:r], s[:r] ** 2, rtol=1e-9, atol=0)
+    assert np.linalg.norm(Bm @ Bm.T - np.eye(r)) <= 1e-8
+    sign = np.sign(np.sum(Bm * vt[:r], axis=1))
+    assert np.linalg.norm(Bm - sign[:, None] * vt[:r]) <= 1e-8 * np.sqrt(r)
+    assert np.linalg.norm(coef - Sc @ Bm.T) <= 1e-9 * np.linalg.norm(coef)
+    # one snapshot: the mean is that snapshot and no mode is kept
+    mean1, basis1, coef1, lam1, r1 = pod_fit(torch.from_numpy(S[:1]).cuda(), 1)
+    assert r1 == 0 and np.array_equal(mean1.cpu().numpy(), S[0]) and lam1[0] == 0.0
 
 
 @pytest.mark.gpu
