@@ -350,7 +350,8 @@ def tm_vs_hb(hbl, torch, log, periods, spp):
 
 
 def learned_warm_start(torch, log, n_train, n_test, K=10, n_rings=12, n_z=90, period=1.0,
-                       max_severity=0.7, batch=1, target="solution", fit_steps=4000):
+                       max_severity=0.7, batch=1, target="solution", fit_steps=4000,
+                       gen_max_newton=80):
     """Learned warm start on the stenosed-pipe family (by default the
     42,679-node mesh, K = 10, severity up to 70 %, 23 parameters): n_train
     solutions generated by the solver (mixed precision to the FP64 residual
@@ -365,7 +366,7 @@ def learned_warm_start(torch, log, n_train, n_test, K=10, n_rings=12, n_z=90, pe
     tt = c4_stenosis_params(n_test, 2025, K=K, max_severity=max_severity)
     Y, Y0, st = learned.generate_snapshots([c4_stenosed(x, K=K, **kw) for x in th], batch=batch,
                                            precision=PRECISIONS["mixed"], log=log,
-                                           max_newton=80, verbose=1)
+                                           max_newton=gen_max_newton, verbose=1)
     th = th[st["kept"]]
     log(f"learned: generated {n_train} solutions in {st['wall_s']:.1f} s ({st})")
     rank = min(64, len(th) // 2)
@@ -424,6 +425,13 @@ def learned_warm_start(torch, log, n_train, n_test, K=10, n_rings=12, n_z=90, pe
         [r["learned"]["r_start"] / r["plain"]["r_start"] for r in rows]))
     log(f"learned warm start: {out}")
     return out
+
+
+def learned_scale(args):
+    if args.learned_scale == "small":
+        return dict(K=2, n_rings=3, n_z=24, period=10.41, max_severity=0.5, batch=128,
+                    gen_max_newton=400)
+    return dict(batch=args.learned_batch)
 
 
 def cfl_study(hbl, torch, log, workload="tjunction", cfls=(0.25, 1.0, 4.0, 16.0), steps=40):
@@ -497,6 +505,9 @@ def main():
     ap.add_argument("--learned-target", choices=["solution", "correction"], default="solution")
     ap.add_argument("--learned-batch", type=int, default=1,
                     help="draws solved together as one disjoint-union mesh")
+    ap.add_argument("--learned-scale", choices=["full", "small"], default="full",
+                    help="full: 42,679 nodes, K = 10, severity <= 0.7; small: 925 nodes, K = 2, "
+                         "Womersley number 4, severity <= 0.5, draws solved 128 at a time")
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned warm-start leg")
     ap.add_argument("--cfl-study", choices=["tjunction", "womersley"], default=None,
@@ -531,8 +542,8 @@ def main():
         return
     if args.learned_only:
         print(json.dumps({"learned_warm_start": learned_warm_start(
-            torch, log, max(args.learned_train, 2), args.learned_test,
-            batch=args.learned_batch, target=args.learned_target)}), flush=True)
+            torch, log, max(args.learned_train, 2), args.learned_test, target=args.learned_target,
+            **learned_scale(args))}), flush=True)
         return
 
     dev = torch.device("cuda:0")
@@ -675,8 +686,8 @@ def main():
     if args.learned_train > 0:
         out["learned_warm_start"] = learned_warm_start(torch, log, args.learned_train,
                                                        args.learned_test,
-                                                       batch=args.learned_batch,
-                                                       target=args.learned_target)
+                                                       target=args.learned_target,
+                                                       **learned_scale(args))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, Y0.cpu().numpy(), V.cpu().numpy())
     gm.close()

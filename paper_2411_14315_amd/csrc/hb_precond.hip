@@ -596,11 +596,46 @@ k_pc_dense_apply(int64_t nc, int nm, const double* __restrict__ Ainv, const T* _
 }
 
 // Samples -> modes: b[a][m][f] = (1/N) sum_s q[a][f][s] e^{-2 pi i m s / N}
-// (m = 0..K), one lane per (node, mode); q has in_ch channels per node.
+// (m = 0..K); q has in_ch channels per node.  One lane per (node, field)
+// with all modes in registers (K + 1 <= PC_MM); the table index is
+// uniform across the wavefront.
+constexpr int PC_MM = 12;
 template <typename TQ, typename T>
 __global__ void __launch_bounds__(PBLK)
 k_pc_to_modes(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
               const double* __restrict__ cs, T* __restrict__ b) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= n * 4) return;
+  const int64_t a = gid >> 2;
+  const int f = (int)(gid & 3);
+  const TQ* qa = q + (a * in_ch + f) * N;
+  double re[PC_MM], im[PC_MM];
+#pragma unroll
+  for (int m = 0; m < PC_MM; ++m) re[m] = im[m] = 0.0;
+  for (int s = 0; s < N; ++s) {
+    const double v = (double)qa[s];
+#pragma unroll
+    for (int m = 0; m < PC_MM; ++m)
+      if (m < nm) {
+        re[m] += v * cs[(m * N + s) * 2];
+        im[m] -= v * cs[(m * N + s) * 2 + 1];
+      }
+  }
+  const double inv = 1.0 / N;
+#pragma unroll
+  for (int m = 0; m < PC_MM; ++m)
+    if (m < nm) {
+      T* p = b + ((a * nm + m) * 4 + f) * 2;
+      p[0] = (T)(re[m] * inv);
+      p[1] = (T)(im[m] * inv);
+    }
+}
+
+// The same for any K: one lane per (node, mode).
+template <typename TQ, typename T>
+__global__ void __launch_bounds__(PBLK)
+k_pc_to_modes_wide(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
+                   const double* __restrict__ cs, T* __restrict__ b) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= n * nm) return;
   const int64_t a = gid / nm;
@@ -620,12 +655,41 @@ k_pc_to_modes(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
   store4(b, gid, out);
 }
 
-// Modes -> samples: z[a][f][s] = Re x_0 + 2 sum_{m>=1} Re(x_m e^{2 pi i m s/N}),
-// one lane per (node, field, sample).
+// Modes -> samples: z[a][f][s] = Re x_0 + 2 sum_{m>=1} Re(x_m e^{2 pi i m s/N}).
+// One lane per (node, field) with the modes in registers (K + 1 <= PC_MM).
 template <typename T, typename TZ>
 __global__ void __launch_bounds__(PBLK)
 k_pc_from_modes(int64_t n, int N, int nm, const T* __restrict__ x,
                 const double* __restrict__ cs, TZ* __restrict__ z) {
+  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
+  if (gid >= n * 4) return;
+  const int64_t a = gid >> 2;
+  const int f = (int)(gid & 3);
+  double xr[PC_MM], xi[PC_MM];
+#pragma unroll
+  for (int m = 0; m < PC_MM; ++m) {
+    xr[m] = xi[m] = 0.0;
+    if (m < nm) {
+      const T* p = x + ((a * nm + m) * 4 + f) * 2;
+      xr[m] = (double)p[0];
+      xi[m] = (double)p[1];
+    }
+  }
+  TZ* za = z + gid * N;
+  for (int s = 0; s < N; ++s) {
+    double v = 0.0;
+#pragma unroll
+    for (int m = 1; m < PC_MM; ++m)
+      if (m < nm) v += xr[m] * cs[(m * N + s) * 2] - xi[m] * cs[(m * N + s) * 2 + 1];
+    za[s] = (TZ)(xr[0] + 2.0 * v);
+  }
+}
+
+// The same for any K: one lane per (node, field, sample).
+template <typename T, typename TZ>
+__global__ void __launch_bounds__(PBLK)
+k_pc_from_modes_wide(int64_t n, int N, int nm, const T* __restrict__ x,
+                     const double* __restrict__ cs, TZ* __restrict__ z) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= n * 4 * N) return;
   const int64_t a = gid / (4 * N);
@@ -641,6 +705,28 @@ k_pc_from_modes(int64_t n, int N, int nm, const T* __restrict__ x,
 }
 
 inline unsigned nblk(int64_t work) { return (unsigned)((work + PBLK - 1) / PBLK); }
+
+template <typename TQ, typename T>
+void launch_to_modes(int64_t n, int N, int nm, const TQ* q, int in_ch, const double* cs, T* b,
+                     hipStream_t st) {
+  if (nm <= PC_MM)
+    hipLaunchKernelGGL((k_pc_to_modes<TQ, T>), dim3(nblk(n * 4)), dim3(PBLK), 0, st, n, N, nm, q,
+                       in_ch, cs, b);
+  else
+    hipLaunchKernelGGL((k_pc_to_modes_wide<TQ, T>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N,
+                       nm, q, in_ch, cs, b);
+}
+
+template <typename T, typename TZ>
+void launch_from_modes(int64_t n, int N, int nm, const T* x, const double* cs, TZ* z,
+                       hipStream_t st) {
+  if (nm <= PC_MM)
+    hipLaunchKernelGGL((k_pc_from_modes<T, TZ>), dim3(nblk(n * 4)), dim3(PBLK), 0, st, n, N, nm, x,
+                       cs, z);
+  else
+    hipLaunchKernelGGL((k_pc_from_modes_wide<T, TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n,
+                       N, nm, x, cs, z);
+}
 
 }  // namespace
 
@@ -1087,14 +1173,12 @@ hipError_t apply_in(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipSt
   using V = LevelVecs<T>;
   const int nm = pc->nm, N = pc->N;
   PcLevel& F = pc->lv[0];
-  hipLaunchKernelGGL((k_pc_to_modes<TQ, T>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm, q,
-                     in_ch, pc->cs.p, V::b(F));
+  launch_to_modes<TQ, T>(n, N, nm, q, in_ch, pc->cs.p, V::b(F), st);
   for (int c = 0; c < pc->cycles; ++c) {
     hipError_t e = vcycle<T>(pc, 0, c == 0, st);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_pc_from_modes<T, TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n, N, nm,
-                     V::x(F), pc->cs.p, z);
+  launch_from_modes<T, TZ>(n, N, nm, V::x(F), pc->cs.p, z, st);
   return hipGetLastError();
 }
 
@@ -1110,12 +1194,10 @@ template <typename TQ, typename TZ>
 hipError_t precond_matvec(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z, hipStream_t st) {
   const int nm = pc->nm, N = pc->N;
   PcLevel& F = pc->lv[0];
-  hipLaunchKernelGGL((k_pc_to_modes<TQ, double>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N, nm,
-                     q, in_ch, pc->cs.p, F.b.p);
+  launch_to_modes<TQ, double>(n, N, nm, q, in_ch, pc->cs.p, F.b.p, st);
   hipLaunchKernelGGL((k_pc_rows<0, double, double>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n,
                      F.rowptr.p, F.col.p, F.diag.p, F.val.p, pc->coef, nullptr, F.b.p, F.x.p, 0.0);
-  hipLaunchKernelGGL((k_pc_from_modes<double, TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n,
-                     N, nm, F.x.p, pc->cs.p, z);
+  launch_from_modes<double, TZ>(n, N, nm, F.x.p, pc->cs.p, z, st);
   return hipGetLastError();
 }
 
