@@ -286,6 +286,12 @@ typedef struct {
                            and transfers on FP32 vectors and coefficients (the
                            coefficients are assembled in FP64 and rounded; the
                            coarsest-level inverse stays FP64)                  */
+  int32_t forcing;      /* GMRES forcing term: 0 gmres_eta at every step; 1 the
+                           Eisenstat-Walker choice 0.9 (|r_k| / |r_k-1|)^2
+                           (safeguarded by 0.9 eta_k-1^2 when that exceeds
+                           0.1), within [gmres_eta / 10, max(gmres_eta, 0.5)]
+                           and no tighter than the Newton target needs;
+                           the first step uses gmres_eta                      */
 } hb_solve_opts;
 
 typedef struct {

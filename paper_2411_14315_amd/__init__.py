@@ -68,7 +68,7 @@ class _Opts(C.Structure):
                 ("reject_ratio", C.c_double), ("dt_growth", C.c_double),
                 ("amg_aggregation", C.c_int32), ("amg_coarse_weight", C.c_double),
                 ("amg_smoother", C.c_int32), ("amg_wcycle", C.c_int32),
-                ("amg_fp32", C.c_int32)]
+                ("amg_fp32", C.c_int32), ("forcing", C.c_int32)]
 
 
 class _PcOpts(C.Structure):
@@ -445,13 +445,15 @@ class SolveOptions:
     amg_smoother: int = 0      # HB_PREC_MEANFLOW: 0 block Jacobi, 1 block Gauss-Seidel
     amg_wcycle: int = 0        # HB_PREC_MEANFLOW: 0 V-cycles, 1 W-cycles
     amg_fp32: int = 0          # HB_PREC_MEANFLOW: 1 cycles on FP32 vectors and coefficients
+    forcing: int = 0           # GMRES forcing: 0 fixed gmres_eta, 1 Eisenstat-Walker
 
     def _c(self):
         return _Opts(self.rtol, self.r_ref, self.gmres_eta, self.cfl, self.c1, self.restart,
                      self.max_newton, self.max_gmres, self.precision, self.jv_kind, self.verbose,
                      self.precond, self.cfl_max, self.graphs, self.amg_sweeps, self.amg_cycles,
                      self.amg_weight, self.reject_ratio, self.dt_growth, self.amg_aggregation,
-                     self.amg_coarse_weight, self.amg_smoother, self.amg_wcycle, self.amg_fp32)
+                     self.amg_coarse_weight, self.amg_smoother, self.amg_wcycle, self.amg_fp32,
+                     self.forcing)
 
 
 def newton_solve(mesh: Mesh, params, bc: BC, Y, opts: SolveOptions | None = None,

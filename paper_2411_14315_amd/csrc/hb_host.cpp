@@ -1492,6 +1492,12 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
     HB_CHECK(m->sb.sysave.ensure(sy_bytes));
     HB_CHECK(m->sb.syfull.ensure(sy_bytes));
   }
+  // forcing term: fixed, or the Eisenstat-Walker choice eta_k =
+  // 0.9 (|r_k| / |r_k-1|)^2, kept above 0.9 eta_k-1^2 when that exceeds 0.1,
+  // within [gmres_eta / 10, max(gmres_eta, 0.5)], and never asking more of
+  // the linear solve than the Newton target (eta |r_k| >= rtol r_ref / 2)
+  double eta = opts->gmres_eta;
+  const double eta_lo = 0.1 * opts->gmres_eta, eta_hi = std::max(opts->gmres_eta, 0.5);
   int status = HB_ERR_NOCONV;
   int it = 0;
   for (;; ++it) {
@@ -1500,6 +1506,8 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
       break;
     }
     if (it >= opts->max_newton) break;
+    if (opts->forcing == 1)
+      eta = std::min(eta_hi, std::max(eta, 0.5 * opts->rtol * ref / std::max(rn, 1e-300)));
     const double shift = opts->c1 * prm->rho / dt;
     const Phys pj = make_phys(prm, shift);
     if (S.use_pc) {
@@ -1517,7 +1525,7 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
                                   w.binv.as<double>(), st));
     }
     int gi = 0;
-    rc = S.gmres(r, shift, opts->gmres_eta, opts->max_gmres, gi);
+    rc = S.gmres(r, shift, eta, opts->max_gmres, gi);
     if (rc) return rc;
     report->gmres_iters += gi;
     double* Sy = w.Sy.as<double>();
@@ -1569,6 +1577,13 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
       double f = rn / std::max(rn_new, 1e-300);
       if (rn_new <= rn) f = std::max(f, grow_min);
       dt = std::min(dt * std::max(f, 0.1), dt_max);
+    }
+    if (opts->forcing == 1) {
+      const double ratio = rn_new / std::max(rn, 1e-300);
+      double e = 0.9 * ratio * ratio;
+      const double keep = 0.9 * eta * eta;
+      if (keep > 0.1) e = std::max(e, keep);
+      eta = std::min(eta_hi, std::max(eta_lo, e));
     }
     rn = rn_new;
   }
@@ -1793,6 +1808,7 @@ int hb_newton_solve(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, 
       (opts->amg_wcycle != 0 && opts->amg_wcycle != 1) ||
       (opts->amg_fp32 != 0 && opts->amg_fp32 != 1))
     return fail(HB_ERR_ARG, "bad multigrid options");
+  if (opts->forcing != 0 && opts->forcing != 1) return fail(HB_ERR_ARG, "forcing must be 0 or 1");
   hb_mesh* m = const_cast<hb_mesh*>(mesh);
   hipStream_t st = (hipStream_t)stream;
   int rc = prepare(m, prm, bc, st);

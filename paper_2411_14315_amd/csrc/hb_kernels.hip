@@ -25,6 +25,7 @@
 // doubles per node and channel.
 #include "hb_internal.h"
 
+#include <atomic>
 #include <type_traits>
 
 namespace hb {
@@ -1462,19 +1463,60 @@ inline unsigned stream_blocks(int64_t L) {
 
 // ------------------------------------------------------------- launchers
 
+// Dynamic LDS of one workgroup allowed on the current device (cached per
+// device); launchers refuse larger requests instead of launching them.
+size_t lds_limit() {
+  static std::atomic<int64_t> cache[64];
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return 65536;
+  int64_t v = cache[d].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int a = 0;
+    if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, d) != hipSuccess ||
+        a <= 0)
+      a = 65536;
+    v = a;
+    cache[d].store(v, std::memory_order_relaxed);
+  }
+  return (size_t)v;
+}
+
+template <typename TI, typename TO, int TL>
+hipError_t modal_to_samples_tl(const DevMesh& m, int N, const TI* Y, const double* dir,
+                               int zero_dirichlet, const double* tab, TO* S, TO* acc_zero,
+                               double* q_zero, int nq, hipStream_t st) {
+  const size_t lds = sizeof(double) * (4 * N * TL + 2 * N * N);
+  if (lds > lds_limit()) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_modal_to_samples<TI, TO, TL>), dim3((unsigned)((m.n + TL - 1) / TL)),
+                     dim3(BLK), lds, st, m.n, N, Y, dir, m.dmask, zero_dirichlet, tab, S, acc_zero,
+                     q_zero, nq);
+  return hipGetLastError();
+}
+
+template <typename TA, typename TO, int TL>
+hipError_t samples_to_modal_tl(const DevMesh& m, int N, const TA* acc, int use_z,
+                               int zero_dir_rows, int in_ch, const double* tab, TO* R,
+                               hipStream_t st) {
+  const size_t lds = sizeof(double) * (TL * in_ch * N + 2 * N * N);
+  if (lds > lds_limit()) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_samples_to_modal<TA, TO, TL>), dim3((unsigned)((m.n + TL - 1) / TL)),
+                     dim3(BLK), lds, st, m.n, N, acc, use_z, zero_dir_rows, in_ch, m.dmask, tab,
+                     R);
+  return hipGetLastError();
+}
+
 template <typename TI, typename TO>
 hipError_t modal_to_samples(const DevMesh& m, int N, const TI* Y, const double* dir,
                             int zero_dirichlet, const double* tab, TO* S, TO* acc_zero,
                             double* q_zero, int nq, hipStream_t st) {
   if (m.n == 0) return hipSuccess;
   // FP64 output: 16-node tiles (more workgroups per CU in flight); FP32
-  // output: 32-node tiles for the 32 x 32 MFMA path
-  constexpr int TL = std::is_same<TO, float>::value ? TN : 16;
-  const size_t lds = sizeof(double) * (4 * N * TL + 2 * N * N);
-  hipLaunchKernelGGL((k_modal_to_samples<TI, TO, TL>), dim3((unsigned)((m.n + TL - 1) / TL)),
-                     dim3(BLK), lds, st, m.n, N, Y, dir, m.dmask, zero_dirichlet, tab, S, acc_zero,
-                     q_zero, nq);
-  return hipGetLastError();
+  // output: 32-node tiles for the 32 x 32 MFMA path (N <= 32), else 16
+  if (std::is_same<TO, float>::value && N <= 32)
+    return modal_to_samples_tl<TI, TO, TN>(m, N, Y, dir, zero_dirichlet, tab, S, acc_zero, q_zero,
+                                           nq, st);
+  return modal_to_samples_tl<TI, TO, 16>(m, N, Y, dir, zero_dirichlet, tab, S, acc_zero, q_zero,
+                                         nq, st);
 }
 
 template <typename TA, typename TO>
@@ -1482,13 +1524,10 @@ hipError_t samples_to_modal(const DevMesh& m, int N, const TA* acc, int use_z, i
                             int in_ch, const double* tab, TO* R, hipStream_t st) {
   if (m.n == 0) return hipSuccess;
   // FP64 output: 16-node tiles (half the LDS, twice the workgroups per CU in
-  // flight); FP32 output: 32-node tiles for the 32 x 32 MFMA path
-  constexpr int TL = std::is_same<TO, float>::value ? TN : 16;
-  const size_t lds = sizeof(double) * (TL * in_ch * N + 2 * N * N);
-  hipLaunchKernelGGL((k_samples_to_modal<TA, TO, TL>), dim3((unsigned)((m.n + TL - 1) / TL)),
-                     dim3(BLK), lds, st, m.n, N, acc, use_z, zero_dir_rows, in_ch, m.dmask, tab,
-                     R);
-  return hipGetLastError();
+  // flight); FP32 output: 32-node tiles for the 32 x 32 MFMA path (N <= 32)
+  if (std::is_same<TO, float>::value && N <= 32)
+    return samples_to_modal_tl<TA, TO, TN>(m, N, acc, use_z, zero_dir_rows, in_ch, tab, R, st);
+  return samples_to_modal_tl<TA, TO, 16>(m, N, acc, use_z, zero_dir_rows, in_ch, tab, R, st);
 }
 
 template <typename TQ, typename TS>
@@ -1496,6 +1535,7 @@ hipError_t prepare_direction(const DevMesh& m, int N, const TQ* q, int in_ch, co
                              const double* binv, int zero_dirichlet, const double* tab, TS* Sv,
                              TS* acc_zero, double* q_zero, int nq, hipStream_t st) {
   const size_t lds = sizeof(double) * (TN * 4 * N + N * N + (binv ? TN * 3 * N : 0));
+  if (lds > lds_limit()) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_prepare<TQ, TS>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, q, in_ch,
                      dinv, binv, zero_dirichlet, m.dmask, tab, Sv, acc_zero, q_zero, nq);
   return hipGetLastError();
@@ -1506,6 +1546,7 @@ hipError_t block_factor(const DevMesh& m, int N, const double* dg, const double*
   if (N < 1 || N > 64) return hipErrorInvalidValue;
   const int P = 64 / N;
   const size_t lds = sizeof(double) * ((size_t)N * N * (1 + P) + (size_t)P * 4 * N);
+  if (lds > lds_limit()) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((m.n + P - 1) / P);
   hipLaunchKernelGGL(k_block_factor, dim3(grid), dim3(64), lds, st, m.n, N, P, dg, mass, rho, tab,
                      m.dmask, binv);
@@ -1516,6 +1557,7 @@ template <typename TA, typename TO>
 hipError_t finish_rows(const DevMesh& m, int N, const TA* acc, int use_z, const double* tab,
                        const TO* id_rows, TO* out, hipStream_t st) {
   const size_t lds = sizeof(double) * (TN * NCH * N + N * N);
+  if (lds > lds_limit()) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_finish<TA, TO>), dim3(tiles(m.n)), dim3(BLK), lds, st, m.n, N, acc, use_z,
                      m.dmask, tab, id_rows, out);
   return hipGetLastError();
@@ -1537,6 +1579,7 @@ hipError_t elem_residual(const DevMesh& m, const Phys& p, const double* S, doubl
                          const ElemBlocks& eb, hipStream_t st) {
   const int64_t nb = (m.ne + eb.size - 1) / eb.size;
   const size_t lds = sizeof(double) * (size_t)eb.max_unique * NCH * p.N;
+  if (lds > lds_limit()) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_elem_block<0, double>), dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, S, S,
                      acc, eb, nb);
   return hipGetLastError();
@@ -1547,6 +1590,7 @@ hipError_t elem_jvp_exact(const DevMesh& m, const Phys& p, const R* Sy, const R*
                           const ElemBlocks& eb, hipStream_t st) {
   const int64_t nb = (m.ne + eb.size - 1) / eb.size;
   const size_t lds = sizeof(double) * (size_t)eb.max_unique * NCH * p.N;
+  if (lds > lds_limit()) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_elem_block<1, R>), dim3(xcd_grid(nb)), dim3(BLK), lds, st, m, p, Sy, Sv,
                      acc, eb, nb);
   return hipGetLastError();

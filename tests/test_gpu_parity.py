@@ -253,6 +253,26 @@ def test_jvp_f32_parity(case, request):
     assert rel(got, ref) <= TOL_F32
 
 
+@pytest.mark.parametrize("K", [15, 16, 32])
+def test_jvp_f32_parity_many_harmonics(K):
+    """FP32 Jv with N = 2K + 1 samples across the matrix-core limit: K = 15
+    (N = 31) takes the split-BF16 MFMA transforms, K = 16 and K = 32 (the
+    largest accepted) the scalar FP32 transforms; 95-node pipe, against the
+    FP64 oracle (the FP64 Jv at 1e-10 beside it)."""
+    P = c1_womersley(K=K, n_rings=2, n_z=4)
+    c = Case(P)
+    Y = seeded_state(P, 40 + K)
+    V = seeded_state(P, 41 + K)
+    om, prm, d, h, R = c.args()
+    print("K", K, "N", prm.N, flush=True)
+    ref = api.jvp_modal(om, prm, Y, V, d, h, R)
+    got = host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V).float())).astype(np.float64)
+    got64 = host(hbl.jvp(c.gm, prm, c.bc, dev(Y), dev(V)))
+    c.gm.close()
+    assert rel(got64, ref) <= TOL
+    assert rel(got, ref) <= TOL_F32
+
+
 @pytest.mark.parametrize("precision", ["mixed", "f32_basis"])
 def test_mixed_solve_matches_oracle_solution(c1, precision):
     """FP32 Krylov basis (with FP32 or FP64 Jv) and the FP64 residual as the
