@@ -56,6 +56,8 @@ enum {
   F_K = 0, F_M = 1, F_T = 2, F_XS = 3, F_G = 4, F_D = 7, F_GP = 10, F_DP = 13, F_L = 16,
   PC_NFIELDS = 17, PC_NF = 18
 };
+// modes held in registers by the one-lane-per-node kernels
+constexpr int PC_MM = 12;
 constexpr double QA_ = 0.58541019662496845446137605030969;
 constexpr double QB_ = 0.13819660112501051517954131656344;
 
@@ -599,7 +601,6 @@ k_pc_dense_apply(int64_t nc, int nm, const double* __restrict__ Ainv, const T* _
 // (m = 0..K); q has in_ch channels per node.  One lane per (node, field)
 // with all modes in registers (K + 1 <= PC_MM); the table index is
 // uniform across the wavefront.
-constexpr int PC_MM = 12;
 template <typename TQ, typename T>
 __global__ void __launch_bounds__(PBLK)
 k_pc_to_modes(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
@@ -1119,6 +1120,16 @@ struct LevelVecs<float> {
   static const float* val(PcLevel& L) { return L.valf.p; }
 };
 
+// Row operation OP on one level, one lane per (node, mode).  (One lane per
+// node, or per group of modes, loads each pair's fields fewer times but
+// keeps fewer waves in flight; it measured slower.)
+template <int OP, typename T>
+void rows(const Precond* pc, const PcLevel& L, const T* val, const T* b, const T* x, T* y,
+          double wj, hipStream_t st) {
+  hipLaunchKernelGGL((k_pc_rows<OP, T, T>), dim3(nblk(L.n * pc->nm)), dim3(PBLK), 0, st, L.n,
+                     L.rowptr.p, L.col.p, L.diag.p, val, pc->coef, b, x, y, wj);
+}
+
 template <typename T>
 hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
   using V = LevelVecs<T>;
@@ -1129,7 +1140,6 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
                        pc->inv.p, V::b(L), V::x(L));
     return hipGetLastError();
   }
-  const unsigned g = nblk(L.n * nm);
   auto sweep = [&](bool from_zero, bool reverse) {
     if (pc->smoother == 1) {
       if (from_zero)
@@ -1145,14 +1155,11 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
       }
       return;
     }
-    hipLaunchKernelGGL((k_pc_rows<2, T, T>), dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
-                       L.diag.p, V::val(L), pc->coef, V::b(L), from_zero ? nullptr : V::x(L),
-                       V::x2(L), pc->wj);
+    rows<2, T>(pc, L, V::val(L), V::b(L), from_zero ? nullptr : V::x(L), V::x2(L), pc->wj, st);
     std::swap(V::x(L), V::x2(L));
   };
   for (int k = 0; k < pc->nu; ++k) sweep(zero_start && k == 0, false);
-  hipLaunchKernelGGL((k_pc_rows<1, T, T>), dim3(g), dim3(PBLK), 0, st, L.n, L.rowptr.p, L.col.p,
-                     L.diag.p, V::val(L), pc->coef, V::b(L), V::x(L), V::r(L), 0.0);
+  rows<1, T>(pc, L, V::val(L), V::b(L), V::x(L), V::r(L), 0.0, st);
   PcLevel& C = pc->lv[l + 1];
   hipLaunchKernelGGL(k_pc_restrict<T>, dim3(nblk(C.n * nm * 8)), dim3(PBLK), 0, st, C.n, nm,
                      L.mptr.p, L.mem.p, V::r(L), V::b(C));
