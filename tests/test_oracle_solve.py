@@ -100,13 +100,14 @@ def test_time_marching_reproduces_hb_orbit():
 def test_womersley_convergence():
     """alpha = 4 pipe (T = 2 pi rho/(16 mu)), exact Womersley inflow, zero
     traction, no slip: the nodal velocity error of the full HB-GLS solution
-    falls at order >= 1.5 under mesh refinement."""
+    falls at order >= 1.5 under mesh refinement, and its divergence (P-div)
+    falls at order >= 0.9 relative to the velocity gradient."""
     K = 1
     rho, mu = 1.06, 0.04
     omega = 16.0 * mu / rho                 # alpha = R sqrt(omega/nu) = 4
     period = 2 * np.pi / omega
     q = np.array([1.0, 0.0, 0.5])           # Q = 1 + 0.5 sin(w t)
-    errs, hs = [], []
+    errs, hs, divs = [], [], []
     for nr, nz in ((2, 4), (4, 8), (8, 16)):
         m = cylinder_mesh(1.0, 6.0, nr, nz)
         prm = Params(K=K, period=period, rho=rho, mu=mu)
@@ -122,9 +123,22 @@ def test_womersley_convergence():
         ex[2] = uz
         errs.append(np.linalg.norm(Y[:3] - ex) / np.linalg.norm(ex))
         hs.append(1.0 / nr)
+        # P-div: the discrete divergence (constant per tet for P1 velocity,
+        # gradients from face normals) in the volume-weighted L2 norm over
+        # the modes, relative to the velocity gradient's norm
+        G, V = pinlib._tet_grads(m.xyz, m.tets)
+        U = Y[:3][:, :, m.tets]                          # (3, N, E, 4)
+        div = np.einsum("eai,inea->ne", G, U)
+        grad = np.einsum("eai,jnea->neij", G, U)
+        divs.append(np.sqrt(np.sum(V * div ** 2) / np.sum(V[None, :, None, None] * grad ** 2)))
     rates = np.log(np.array(errs[:-1]) / np.array(errs[1:])) / np.log(2.0)
     assert rates[-1] >= 1.5, (errs, rates)
     assert errs[-1] < 0.05, errs
+    # the PSPG-stabilised P1-P1 velocity is not pointwise divergence free; its
+    # divergence falls with h (at least first order relative to the gradient)
+    drates = np.log(np.array(divs[:-1]) / np.array(divs[1:])) / np.log(2.0)
+    print("velocity error", errs, "divergence", divs, "rates", rates, drates)
+    assert np.all(drates >= 0.9), (divs, drates)
 
 
 def test_steady_boundary_data_give_time_independent_solution():
