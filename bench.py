@@ -436,9 +436,9 @@ def learned_scale(args):
 
 def cfl_study(hbl, torch, log, workload="tjunction", cfls=(0.25, 1.0, 4.0, 16.0), steps=40):
     """Pseudo-time step study (Section 2.3 sets dt ~ h_c / u_c): FP64 Newton
-    steps from the plain start with the pseudo step held fixed at
-    dt = cfl h_c / u_c (no growth), recording the residual relative to the
-    plain start's after every step."""
+    steps (mean-flow multigrid) from the plain start with the pseudo step
+    held fixed at dt = cfl h_c / u_c (no growth), recording the residual
+    relative to the plain start's after every step."""
     from dataclasses import replace
     from hbinputs.problems import c1_womersley, c2_tjunction
     P = c2_tjunction(K=10) if workload == "tjunction" else c1_womersley()
@@ -450,17 +450,16 @@ def cfl_study(hbl, torch, log, workload="tjunction", cfls=(0.25, 1.0, 4.0, 16.0)
     bc0 = hbl.BC(to(P.dirichlet[:, :1]), P.outlet_h[:, :1], P.outlet_R)
     Ys = torch.zeros((4, 1, n), dtype=torch.float64, device="cuda:0")
     hbl.newton_solve(gm, replace(prm, K=0), bc0, Ys,
-                     hbl.SolveOptions(rtol=1e-10, max_newton=30, max_gmres=300),
-                     raise_on_noconv=False)
+                     solve_opts(hbl, rtol=1e-10, max_newton=60), raise_on_noconv=False)
     Y0 = torch.zeros((4, N, n), dtype=torch.float64, device="cuda:0")
     Y0[:, 0] = Ys[:, 0]
-    r0 = hbl.newton_solve(gm, prm, bc, Y0.clone(), hbl.SolveOptions(max_newton=0),
+    r0 = hbl.newton_solve(gm, prm, bc, Y0.clone(), solve_opts(hbl, max_newton=0),
                           raise_on_noconv=False)["r0"]
     out = {"workload": workload, "n_nodes": n, "K": prm.K, "steps": steps, "runs": {}}
     for cfl in cfls:
         Y = Y0.clone()
-        opts = hbl.SolveOptions(rtol=1e-30, r_ref=r0, max_newton=1, max_gmres=300, cfl=cfl,
-                                cfl_max=cfl)
+        opts = solve_opts(hbl, rtol=1e-30, r_ref=r0, max_newton=1, max_gmres=300, cfl=cfl,
+                          cfl_max=cfl)
         hist, gm_its = [], 0
         torch.cuda.synchronize()
         t = time.time()
