@@ -304,17 +304,38 @@ __device__ __forceinline__ void block_solve(const PairOp<T>& o, const cplxT<T> r
   for (int f = 0; f < 3; ++f) e[f] = cdiv(csub(r[f], cmul(o.g[f], e[3])), o.kap);
 }
 
+// A pending coarse-level correction of x: the fine vector is read as
+// x_j + gamma xc[agg[j]] (xc = NULL: plain x).
+template <typename T>
+struct Corr {
+  const T* xc;
+  const int32_t* agg;
+  T gamma;
+};
+template <typename T>
+__device__ __forceinline__ void load_x(const T* __restrict__ x, const Corr<T>& cr, int64_t j,
+                                       int m, int nm, cplxT<T> out[4]) {
+  load4(x, j * nm + m, out);
+  if (cr.xc) {
+    cplxT<T> e[4];
+    load4(cr.xc, (int64_t)cr.agg[j] * nm + m, e);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) out[f] = {out[f].re + cr.gamma * e[f].re, out[f].im + cr.gamma * e[f].im};
+  }
+}
+
 // acc += A_row(i) x for one mode
 template <typename T, typename M>
 __device__ __forceinline__ void row_apply(int64_t i, int m, const int32_t* __restrict__ rowptr,
                                           const int32_t* __restrict__ col,
                                           const M* __restrict__ val, const Coef& c, T s,
-                                          const T* __restrict__ x, cplxT<T> acc[4]) {
+                                          const T* __restrict__ x, const Corr<T>& cr,
+                                          cplxT<T> acc[4]) {
   for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
     const int64_t j = col[k];
     const PairOp<T> o = pair_op<T, M>(val + (int64_t)k * PC_NF, c, s);
     cplxT<T> xj[4];
-    load4(x, j * c.nm + m, xj);
+    load_x(x, cr, j, m, c.nm, xj);
 #pragma unroll
     for (int f = 0; f < 3; ++f)
       acc[f] = cadd(acc[f], cadd(cmul(o.kap, xj[f]), cmul(o.g[f], xj[3])));
@@ -325,19 +346,21 @@ __device__ __forceinline__ void row_apply(int64_t i, int m, const int32_t* __res
 
 // Row operation on all modes, one lane per (node, mode):
 //   OP 0: y = A x;  OP 1: y = b - A x;
-//   OP 2: y = x + w D^-1 (b - A x) (x = NULL: y = w D^-1 b), D the nodal block.
+//   OP 2: y = x + w D^-1 (b - A x) (x = NULL: y = w D^-1 b), D the nodal block;
+// with a pending coarse correction cr, x stands for x + gamma P xc.
 template <int OP, typename T, typename M>
 __global__ void __launch_bounds__(PBLK)
 k_pc_rows(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
           const int32_t* __restrict__ diag, const M* __restrict__ val, Coef c,
-          const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ y, double wj) {
+          const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ y, double wj,
+          Corr<T> cr) {
   const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
   if (gid >= n * c.nm) return;
   const int64_t i = gid / c.nm;
   const int m = (int)(gid - i * c.nm);
   const T s = (T)(m * c.omega);
   cplxT<T> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  if (x) row_apply<T, M>(i, m, rowptr, col, val, c, s, x, acc);
+  if (x) row_apply<T, M>(i, m, rowptr, col, val, c, s, x, cr, acc);
   if (OP == 0) {
     store4(y, gid, acc);
     return;
@@ -353,7 +376,7 @@ k_pc_rows(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restri
   cplxT<T> e[4];
   block_solve(pair_op<T, M>(val + (int64_t)diag[i] * PC_NF, c, s), r, e);
   cplxT<T> out[4];
-  if (x) load4(x, gid, out);
+  if (x) load_x(x, cr, i, m, c.nm, out);
   else out[0] = out[1] = out[2] = out[3] = {(T)0, (T)0};
   const T w = (T)wj;
 #pragma unroll
@@ -376,7 +399,7 @@ k_pc_gs(int64_t nrows, const int32_t* __restrict__ rows, const int32_t* __restri
   const int64_t i = rows[li];
   const T s = (T)(m * c.omega);
   cplxT<T> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  row_apply<T, M>(i, m, rowptr, col, val, c, s, x, acc);
+  row_apply<T, M>(i, m, rowptr, col, val, c, s, x, Corr<T>{nullptr, nullptr, (T)0}, acc);
   cplxT<T> r[4];
   load4(b, i * c.nm + m, r);
 #pragma unroll
@@ -1125,9 +1148,9 @@ struct LevelVecs<float> {
 // keeps fewer waves in flight; it measured slower.)
 template <int OP, typename T>
 void rows(const Precond* pc, const PcLevel& L, const T* val, const T* b, const T* x, T* y,
-          double wj, hipStream_t st) {
+          double wj, hipStream_t st, Corr<T> cr = {nullptr, nullptr, (T)0}) {
   hipLaunchKernelGGL((k_pc_rows<OP, T, T>), dim3(nblk(L.n * pc->nm)), dim3(PBLK), 0, st, L.n,
-                     L.rowptr.p, L.col.p, L.diag.p, val, pc->coef, b, x, y, wj);
+                     L.rowptr.p, L.col.p, L.diag.p, val, pc->coef, b, x, y, wj, cr);
 }
 
 template <typename T>
@@ -1140,6 +1163,7 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
                        pc->inv.p, V::b(L), V::x(L));
     return hipGetLastError();
   }
+  Corr<T> cr{nullptr, nullptr, (T)0};
   auto sweep = [&](bool from_zero, bool reverse) {
     if (pc->smoother == 1) {
       if (from_zero)
@@ -1155,7 +1179,8 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
       }
       return;
     }
-    rows<2, T>(pc, L, V::val(L), V::b(L), from_zero ? nullptr : V::x(L), V::x2(L), pc->wj, st);
+    rows<2, T>(pc, L, V::val(L), V::b(L), from_zero ? nullptr : V::x(L), V::x2(L), pc->wj, st,
+               cr);
     std::swap(V::x(L), V::x2(L));
   };
   for (int k = 0; k < pc->nu; ++k) sweep(zero_start && k == 0, false);
@@ -1169,9 +1194,17 @@ hipError_t vcycle(Precond* pc, size_t l, bool zero_start, hipStream_t st) {
     e = vcycle<T>(pc, l + 1, false, st);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_pc_prolong<T>, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st, L.n, nm,
-                     L.agg.p, V::x(C), V::x(L), pc->gamma);
-  for (int k = 0; k < pc->nu; ++k) sweep(false, true);
+  if (pc->smoother == 1) {
+    hipLaunchKernelGGL(k_pc_prolong<T>, dim3(nblk(L.n * nm * 8)), dim3(PBLK), 0, st, L.n, nm,
+                       L.agg.p, V::x(C), V::x(L), pc->gamma);
+    for (int k = 0; k < pc->nu; ++k) sweep(false, true);
+  } else {
+    // the first post-smoothing sweep reads x + gamma P xc (the prolongation)
+    cr = {V::x(C), L.agg.p, (T)pc->gamma};
+    sweep(false, true);
+    cr = {nullptr, nullptr, (T)0};
+    for (int k = 1; k < pc->nu; ++k) sweep(false, true);
+  }
   return hipGetLastError();
 }
 
@@ -1203,7 +1236,8 @@ hipError_t precond_matvec(Precond* pc, int64_t n, const TQ* q, int in_ch, TZ* z,
   PcLevel& F = pc->lv[0];
   launch_to_modes<TQ, double>(n, N, nm, q, in_ch, pc->cs.p, F.b.p, st);
   hipLaunchKernelGGL((k_pc_rows<0, double, double>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n,
-                     F.rowptr.p, F.col.p, F.diag.p, F.val.p, pc->coef, nullptr, F.b.p, F.x.p, 0.0);
+                     F.rowptr.p, F.col.p, F.diag.p, F.val.p, pc->coef, nullptr, F.b.p, F.x.p, 0.0,
+                     Corr<double>{nullptr, nullptr, 0.0});
   launch_from_modes<double, TZ>(n, N, nm, F.x.p, pc->cs.p, z, st);
   return hipGetLastError();
 }
