@@ -1297,6 +1297,110 @@ k_mdots(const T* __restrict__ Q, int64_t ld, int k, const T* __restrict__ w, int
   }
 }
 
+// 16-byte packs of Krylov vector entries (4 FP32 or 2 FP64 values): one
+// load or store instruction moves a full 16 bytes per lane.
+template <typename T>
+struct alignas(16) Pack16 {
+  static constexpr int W = 16 / sizeof(T);
+  T v[W];
+};
+
+// k_mdots on 16-byte packs (L and ld multiples of the pack width, vectors
+// 16-byte aligned).
+template <int G, typename T>
+__global__ void __launch_bounds__(BLK)
+k_mdots_v(const T* __restrict__ Q, int64_t ld, int k, const T* __restrict__ w, int64_t L,
+          double* __restrict__ partial) {
+  using P = Pack16<T>;
+  __shared__ double red[BLK / 64];
+  const int k0 = blockIdx.y * G;
+  const int kc = min(G, k - k0);
+  const int nb = gridDim.x;
+  const int64_t nc = L / P::W, ldc = ld / P::W;
+  const P* Qp = reinterpret_cast<const P*>(Q);
+  const P* wp = reinterpret_cast<const P*>(w);
+  double acc[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc[j] = 0.0;
+  const int64_t stride = (int64_t)nb * BLK;
+  for (int64_t c = (int64_t)blockIdx.x * BLK + threadIdx.x; c < nc; c += stride) {
+    const P wc = wp[c];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < kc) {
+        const P q = Qp[(int64_t)(k0 + j) * ldc + c];
+#pragma unroll
+        for (int e = 0; e < P::W; ++e) acc[j] += (double)q.v[e] * (double)wc.v[e];
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const double t = block_sum(acc[j], red);
+    if (threadIdx.x == 0 && j < kc) partial[(int64_t)(k0 + j) * nb + blockIdx.x] = t;
+  }
+}
+
+// k_axpy_norm on 16-byte packs.
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_axpy_norm_v(T* __restrict__ w, const T* __restrict__ Q, int64_t ld, int k,
+              const double* __restrict__ h, int64_t L, double* __restrict__ partial) {
+  using P = Pack16<T>;
+  __shared__ double red[BLK / 64];
+  const int64_t nc = L / P::W, ldc = ld / P::W;
+  const P* Qp = reinterpret_cast<const P*>(Q);
+  P* wp = reinterpret_cast<P*>(w);
+  double s2 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t c = (int64_t)blockIdx.x * BLK + threadIdx.x; c < nc; c += stride) {
+    double v[P::W];
+#pragma unroll
+    for (int e = 0; e < P::W; ++e) v[e] = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const P q = Qp[(int64_t)j * ldc + c];
+      const double hj = h[j];
+#pragma unroll
+      for (int e = 0; e < P::W; ++e) v[e] += hj * (double)q.v[e];
+    }
+    P wc = wp[c];
+#pragma unroll
+    for (int e = 0; e < P::W; ++e) {
+      wc.v[e] = (T)((double)wc.v[e] - v[e]);
+      s2 += (double)wc.v[e] * (double)wc.v[e];
+    }
+    wp[c] = wc;
+  }
+  const double t = block_sum(s2, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// k_axpy_multi on 16-byte packs.
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_axpy_multi_v(T* __restrict__ w, const T* __restrict__ Q, int64_t ld, int k,
+               const double* __restrict__ h, double sign, int64_t L) {
+  using P = Pack16<T>;
+  const int64_t nc = L / P::W, ldc = ld / P::W;
+  const P* Qp = reinterpret_cast<const P*>(Q);
+  P* wp = reinterpret_cast<P*>(w);
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t c = (int64_t)blockIdx.x * BLK + threadIdx.x; c < nc; c += stride) {
+    double v[P::W];
+#pragma unroll
+    for (int e = 0; e < P::W; ++e) v[e] = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const P q = Qp[(int64_t)j * ldc + c];
+      const double hj = h[j];
+#pragma unroll
+      for (int e = 0; e < P::W; ++e) v[e] += hj * (double)q.v[e];
+    }
+    P wc = wp[c];
+#pragma unroll
+    for (int e = 0; e < P::W; ++e) wc.v[e] = (T)((double)wc.v[e] + sign * v[e]);
+    wp[c] = wc;
+  }
+}
+
 // w -= sum_j h_j Q_j, with per-workgroup partials of |w|^2 of the result in
 // partial[blockIdx.x] (k_reduce_rows finishes the sum).
 template <typename T>
@@ -1648,6 +1752,13 @@ hipError_t vec_dots(const T* Q, int64_t ld, int k, const T* w, int64_t L, double
   return hipGetLastError();
 }
 
+// The 16-byte pack kernels apply: whole packs, aligned rows.
+template <typename T>
+bool packable(int64_t L, int64_t ld, const T* Q, const T* w) {
+  constexpr int W = Pack16<T>::W;
+  return L % W == 0 && ld % W == 0 && ((uintptr_t)Q & 15) == 0 && ((uintptr_t)w & 15) == 0;
+}
+
 // workgroups per vector slice for the fused reductions: >= 4 elements per
 // lane, at most nblk
 inline unsigned red_blocks(int64_t L, int nblk) {
@@ -1660,8 +1771,12 @@ hipError_t vec_mdots(const T* Q, int64_t ld, int k, const T* w, int64_t L, doubl
                      int nblk, double* out, hipStream_t st) {
   const unsigned nb = red_blocks(L, nblk);
   const unsigned groups = (unsigned)((k + 7) / 8);
-  hipLaunchKernelGGL((k_mdots<8, T>), dim3(nb, groups), dim3(BLK), 0, st, Q, ld, k, w, L,
-                     partial);
+  if (packable<T>(L, ld, Q, w))
+    hipLaunchKernelGGL((k_mdots_v<8, T>), dim3(nb, groups), dim3(BLK), 0, st, Q, ld, k, w, L,
+                       partial);
+  else
+    hipLaunchKernelGGL((k_mdots<8, T>), dim3(nb, groups), dim3(BLK), 0, st, Q, ld, k, w, L,
+                       partial);
   hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(BLK), 0, st, partial, (int)nb, out);
   return hipGetLastError();
 }
@@ -1670,7 +1785,11 @@ template <typename T>
 hipError_t vec_axpy_norm(T* w, const T* Q, int64_t ld, int k, const double* h, int64_t L,
                          double* partial, int nblk, double* out, hipStream_t st) {
   const unsigned nb = stream_blocks(L) < (unsigned)nblk ? stream_blocks(L) : (unsigned)nblk;
-  hipLaunchKernelGGL((k_axpy_norm<T>), dim3(nb), dim3(BLK), 0, st, w, Q, ld, k, h, L, partial);
+  if (packable<T>(L, ld, Q, w))
+    hipLaunchKernelGGL((k_axpy_norm_v<T>), dim3(nb), dim3(BLK), 0, st, w, Q, ld, k, h, L,
+                       partial);
+  else
+    hipLaunchKernelGGL((k_axpy_norm<T>), dim3(nb), dim3(BLK), 0, st, w, Q, ld, k, h, L, partial);
   hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(BLK), 0, st, partial, (int)nb, out);
   return hipGetLastError();
 }
@@ -1678,8 +1797,12 @@ hipError_t vec_axpy_norm(T* w, const T* Q, int64_t ld, int k, const double* h, i
 template <typename T>
 hipError_t vec_axpy_multi(T* w, const T* Q, int64_t ld, int k, const double* h, double sign,
                           int64_t L, hipStream_t st) {
-  hipLaunchKernelGGL((k_axpy_multi<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, w, Q, ld, k, h,
-                     sign, L);
+  if (packable<T>(L, ld, Q, w))
+    hipLaunchKernelGGL((k_axpy_multi_v<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, w, Q, ld,
+                       k, h, sign, L);
+  else
+    hipLaunchKernelGGL((k_axpy_multi<T>), dim3(stream_blocks(L)), dim3(BLK), 0, st, w, Q, ld, k,
+                       h, sign, L);
   return hipGetLastError();
 }
 
