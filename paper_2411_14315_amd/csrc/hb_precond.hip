@@ -621,38 +621,57 @@ k_pc_dense_apply(int64_t nc, int nm, const double* __restrict__ Ainv, const T* _
 }
 
 // Samples -> modes: b[a][m][f] = (1/N) sum_s q[a][f][s] e^{-2 pi i m s / N}
-// (m = 0..K); q has in_ch channels per node.  One lane per (node, field)
-// with all modes in registers (K + 1 <= PC_MM); the table index is
-// uniform across the wavefront.
+// (m = 0..K); q has in_ch channels per node.  A workgroup takes PC_TN
+// nodes: their 4 N samples are staged in LDS with contiguous loads, one lane
+// per (node, field) transforms with all modes in registers (K + 1 <= PC_MM;
+// the table index is uniform across the wavefront), and the modal tile goes
+// back through LDS to contiguous stores.  LDS: PC_TN max(4 N, 8 (K + 1))
+// values.
+constexpr int PC_TN = PBLK / 4;
 template <typename TQ, typename T>
 __global__ void __launch_bounds__(PBLK)
 k_pc_to_modes(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch,
               const double* __restrict__ cs, T* __restrict__ b) {
-  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
-  if (gid >= n * 4) return;
-  const int64_t a = gid >> 2;
-  const int f = (int)(gid & 3);
-  const TQ* qa = q + (a * in_ch + f) * N;
+  extern __shared__ double sbuf[];
+  const int64_t a0 = (int64_t)blockIdx.x * PC_TN;
+  const int tn = (int)min<int64_t>(PC_TN, n - a0);
+  const int t = threadIdx.x;
+  const int NS = 4 * N;
+  for (int idx = t; idx < tn * NS; idx += PBLK) {
+    const int al = idx / NS;
+    sbuf[idx] = (double)q[(a0 + al) * in_ch * N + (idx - al * NS)];
+  }
+  __syncthreads();
+  const int al = t >> 2, f = t & 3;
   double re[PC_MM], im[PC_MM];
 #pragma unroll
   for (int m = 0; m < PC_MM; ++m) re[m] = im[m] = 0.0;
-  for (int s = 0; s < N; ++s) {
-    const double v = (double)qa[s];
+  if (al < tn) {
+    const double* qa = sbuf + (al * 4 + f) * N;
+    for (int s = 0; s < N; ++s) {
+      const double v = qa[s];
+#pragma unroll
+      for (int m = 0; m < PC_MM; ++m)
+        if (m < nm) {
+          re[m] += v * cs[(m * N + s) * 2];
+          im[m] -= v * cs[(m * N + s) * 2 + 1];
+        }
+    }
+  }
+  __syncthreads();
+  const double inv = 1.0 / N;
+  if (al < tn) {
 #pragma unroll
     for (int m = 0; m < PC_MM; ++m)
       if (m < nm) {
-        re[m] += v * cs[(m * N + s) * 2];
-        im[m] -= v * cs[(m * N + s) * 2 + 1];
+        double* p = sbuf + ((al * nm + m) * 4 + f) * 2;
+        p[0] = re[m] * inv;
+        p[1] = im[m] * inv;
       }
   }
-  const double inv = 1.0 / N;
-#pragma unroll
-  for (int m = 0; m < PC_MM; ++m)
-    if (m < nm) {
-      T* p = b + ((a * nm + m) * 4 + f) * 2;
-      p[0] = (T)(re[m] * inv);
-      p[1] = (T)(im[m] * inv);
-    }
+  __syncthreads();
+  T* bt = b + a0 * nm * 8;
+  for (int idx = t; idx < tn * nm * 8; idx += PBLK) bt[idx] = (T)sbuf[idx];
 }
 
 // The same for any K: one lane per (node, mode).
@@ -680,33 +699,45 @@ k_pc_to_modes_wide(int64_t n, int N, int nm, const TQ* __restrict__ q, int in_ch
 }
 
 // Modes -> samples: z[a][f][s] = Re x_0 + 2 sum_{m>=1} Re(x_m e^{2 pi i m s/N}).
-// One lane per (node, field) with the modes in registers (K + 1 <= PC_MM).
+// Staged like k_pc_to_modes: the tile's modes in through LDS, one lane per
+// (node, field) with the modes in registers (K + 1 <= PC_MM), the samples
+// out through LDS.
 template <typename T, typename TZ>
 __global__ void __launch_bounds__(PBLK)
 k_pc_from_modes(int64_t n, int N, int nm, const T* __restrict__ x,
                 const double* __restrict__ cs, TZ* __restrict__ z) {
-  const int64_t gid = (int64_t)blockIdx.x * PBLK + threadIdx.x;
-  if (gid >= n * 4) return;
-  const int64_t a = gid >> 2;
-  const int f = (int)(gid & 3);
+  extern __shared__ double sbuf[];
+  const int64_t a0 = (int64_t)blockIdx.x * PC_TN;
+  const int tn = (int)min<int64_t>(PC_TN, n - a0);
+  const int t = threadIdx.x;
+  const T* xt = x + a0 * nm * 8;
+  for (int idx = t; idx < tn * nm * 8; idx += PBLK) sbuf[idx] = (double)xt[idx];
+  __syncthreads();
+  const int al = t >> 2, f = t & 3;
   double xr[PC_MM], xi[PC_MM];
 #pragma unroll
   for (int m = 0; m < PC_MM; ++m) {
     xr[m] = xi[m] = 0.0;
-    if (m < nm) {
-      const T* p = x + ((a * nm + m) * 4 + f) * 2;
-      xr[m] = (double)p[0];
-      xi[m] = (double)p[1];
+    if (al < tn && m < nm) {
+      const double* p = sbuf + ((al * nm + m) * 4 + f) * 2;
+      xr[m] = p[0];
+      xi[m] = p[1];
     }
   }
-  TZ* za = z + gid * N;
-  for (int s = 0; s < N; ++s) {
-    double v = 0.0;
+  __syncthreads();
+  if (al < tn) {
+    double* za = sbuf + (al * 4 + f) * N;
+    for (int s = 0; s < N; ++s) {
+      double v = 0.0;
 #pragma unroll
-    for (int m = 1; m < PC_MM; ++m)
-      if (m < nm) v += xr[m] * cs[(m * N + s) * 2] - xi[m] * cs[(m * N + s) * 2 + 1];
-    za[s] = (TZ)(xr[0] + 2.0 * v);
+      for (int m = 1; m < PC_MM; ++m)
+        if (m < nm) v += xr[m] * cs[(m * N + s) * 2] - xi[m] * cs[(m * N + s) * 2 + 1];
+      za[s] = xr[0] + 2.0 * v;
+    }
   }
+  __syncthreads();
+  TZ* zt = z + a0 * 4 * N;
+  for (int idx = t; idx < tn * 4 * N; idx += PBLK) zt[idx] = (TZ)sbuf[idx];
 }
 
 // The same for any K: one lane per (node, field, sample).
@@ -730,12 +761,17 @@ k_pc_from_modes_wide(int64_t n, int N, int nm, const T* __restrict__ x,
 
 inline unsigned nblk(int64_t work) { return (unsigned)((work + PBLK - 1) / PBLK); }
 
+// LDS of one mode-transform tile: PC_TN nodes x max(4 N, 8 (K + 1)) values
+inline size_t tile_lds(int N, int nm) {
+  return sizeof(double) * PC_TN * (size_t)(4 * N > 8 * nm ? 4 * N : 8 * nm);
+}
+
 template <typename TQ, typename T>
 void launch_to_modes(int64_t n, int N, int nm, const TQ* q, int in_ch, const double* cs, T* b,
                      hipStream_t st) {
   if (nm <= PC_MM)
-    hipLaunchKernelGGL((k_pc_to_modes<TQ, T>), dim3(nblk(n * 4)), dim3(PBLK), 0, st, n, N, nm, q,
-                       in_ch, cs, b);
+    hipLaunchKernelGGL((k_pc_to_modes<TQ, T>), dim3((unsigned)((n + PC_TN - 1) / PC_TN)),
+                       dim3(PBLK), tile_lds(N, nm), st, n, N, nm, q, in_ch, cs, b);
   else
     hipLaunchKernelGGL((k_pc_to_modes_wide<TQ, T>), dim3(nblk(n * nm)), dim3(PBLK), 0, st, n, N,
                        nm, q, in_ch, cs, b);
@@ -745,8 +781,8 @@ template <typename T, typename TZ>
 void launch_from_modes(int64_t n, int N, int nm, const T* x, const double* cs, TZ* z,
                        hipStream_t st) {
   if (nm <= PC_MM)
-    hipLaunchKernelGGL((k_pc_from_modes<T, TZ>), dim3(nblk(n * 4)), dim3(PBLK), 0, st, n, N, nm, x,
-                       cs, z);
+    hipLaunchKernelGGL((k_pc_from_modes<T, TZ>), dim3((unsigned)((n + PC_TN - 1) / PC_TN)),
+                       dim3(PBLK), tile_lds(N, nm), st, n, N, nm, x, cs, z);
   else
     hipLaunchKernelGGL((k_pc_from_modes_wide<T, TZ>), dim3(nblk(n * 4 * N)), dim3(PBLK), 0, st, n,
                        N, nm, x, cs, z);
