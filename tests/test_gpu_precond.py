@@ -148,6 +148,25 @@ def test_solve_meanflow_matches_oracle_solution(c1, precision):
     assert reps[hbl.HB_PREC_MEANFLOW]["gmres_iters"] < reps[hbl.HB_PREC_NODE_TIME]["gmres_iters"]
 
 
+def test_solve_with_adaptive_forcing_reaches_the_same_root(c1):
+    """The Eisenstat-Walker forcing term (forcing = 1) changes only how
+    tightly each linear system is solved: the solve reaches the stored
+    oracle root at 1e-10; a forcing code other than 0 or 1 is rejected."""
+    g = np.load(os.path.join(HERE, "golden", "c1_solution.npz"))
+    P = c1.P
+    Y = dev(g["Y0"])
+    rep = hbl.newton_solve(c1.gm, P.params, c1.bc, Y,
+                           hbl.SolveOptions(rtol=1e-12, max_newton=400, max_gmres=1000,
+                                            precond=hbl.HB_PREC_MEANFLOW, forcing=1))
+    print("forcing 1:", rep["newton_iters"], rep["gmres_iters"], flush=True)
+    assert rep["status"] == 0
+    assert rel(host(Y), g["Y"]) <= TOL
+    with pytest.raises(hbl.HBError) as e:
+        hbl.newton_solve(c1.gm, P.params, c1.bc, dev(g["Y0"]),
+                         hbl.SolveOptions(precond=hbl.HB_PREC_MEANFLOW, forcing=2))
+    assert e.value.status == hbl.HB_ERR_ARG
+
+
 def test_precond_argument_errors(tiny):
     c = tiny
     Y = dev(seeded_state(c.P, 0))
@@ -156,6 +175,9 @@ def test_precond_argument_errors(tiny):
     assert e.value.status == hbl.HB_ERR_ARG
     with pytest.raises(hbl.HBError) as e:
         hbl.precond_apply(c.gm, c.P.params, c.bc, Y, Y.clone(), -1.0)
+    assert e.value.status == hbl.HB_ERR_ARG
+    with pytest.raises(hbl.HBError) as e:
+        hbl.precond_apply(c.gm, c.P.params, c.bc, Y, Y.clone(), fp32=2)
     assert e.value.status == hbl.HB_ERR_ARG
     with pytest.raises(hbl.HBError) as e:
         hbl.precond_apply(c.gm, c.P.params, c.bc, Y, Y.float())
