@@ -58,9 +58,9 @@ FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 # FP64 operations per (tetrahedron, sample) lane of the exact-Jv element
 # kernel: counted by rocprofv3 (FP64 VALU instructions of each kind x 64
-# lanes, FMA = 2) and, for comparison, the survey-style estimate of the
-# algorithm (primal + tangent).
-ELEM_FLOPS_SURVEY = 2700
+# lanes, FMA = 2) and, for comparison, an estimate counted from the
+# equations (primal + tangent, about 1.2k + 1.5k flop).
+ELEM_FLOPS_EQUATIONS = 2700
 ELEM_FLOPS = {"sha256_prefix": "85dde60c62f4d23e", "per_tet_sample": 1953.5,
               "source": "rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes (FMA = 2), "
                         "profiles/k_elem_jvp_exact_branching_K10_counters.md"}
@@ -623,7 +623,7 @@ def main():
                 "frac": flops / (elem_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                 "traffic": None, "kernel": "k_elem_block<1,double> (exact Jv)",
                 "kernel_ms": elem_ms, "flop_per_lane": per_lane, "flop_source": flop_src,
-                "frac_survey_count": ELEM_FLOPS_SURVEY * ne * N / (elem_ms * 1e-3) / 1e12
+                "frac_equation_count": ELEM_FLOPS_EQUATIONS * ne * N / (elem_ms * 1e-3) / 1e12
                 / FP64_PEAK_TFLOPS,
                 "hbm_algorithmic_GBs": elem_bytes(n, ne, N) / (elem_ms * 1e-3) / 1e9}
     traffic, traffic_detail = elem_traffic(n, ne, prm.K)
