@@ -126,18 +126,20 @@ def test_steady_K0(c1):
     assert rel(got, ref) <= TOL
 
 
-def test_full_size_sampled_rows(tj_full):
-    """Full-size T-junction (the benchmarked workload): rows of 64 seeded
-    random nodes, computed one by one by the oracle from the elements and
-    faces that touch them."""
+@pytest.mark.parametrize("seed,noise", [(9, 0.1), (23, 0.0), (25, 1.0)])
+def test_full_size_sampled_rows(tj_full, seed, noise):
+    """Full-size T-junction: rows of 64 seeded random nodes (and the nodes
+    of 8 outlet faces), computed one by one by the oracle from the elements
+    and faces that touch them, at three seeded states (smooth, smooth plus
+    10 % noise, noise as large as the smooth part)."""
     c = tj_full
     om, prm, d, h, R = c.args()
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     rows = np.sort(rng.choice(om.n, 64, replace=False))
     # include outlet-face nodes so the traction/backflow/resistance rows are sampled
     rows = np.union1d(rows, om.ofaces[rng.choice(om.ofaces.shape[0], 8, replace=False)].ravel())
-    Y = seeded_state(c.P, 9)
-    V = seeded_state(c.P, 10)
+    Y = seeded_state(c.P, seed, noise=noise)
+    V = seeded_state(c.P, seed + 1, noise=noise)
     ref = api.residual_modal(om, prm, Y, d, h, R, rows=rows)[:, :, rows]
     got = host(hbl.residual(c.gm, prm, c.bc, dev(Y)))[:, :, rows]
     assert rel(got, ref) <= TOL
