@@ -39,5 +39,51 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+SAN_DIR = os.path.join(HERE, "_san")
+SAN_LIB = os.path.join(SAN_DIR, "libhb_san.so")
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's AddressSanitizer runtime (for LD_PRELOAD)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    out = subprocess.run([os.path.join(rocm, "llvm", "bin", "clang"),
+                          "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True, check=True)
+    return out.stdout.strip()
+
+
+def build_sanitized(verbose: bool = True) -> str:
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    in its host code only (the device code is built as usual), -O1, for
+    running the host-side entry points (argument and mesh checks, the
+    eigensolver) under the sanitizers on a machine without a GPU."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    common = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-Xarch_host", "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"),
+              "-I", CSRC] + san
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(SAN_DIR, src.rsplit(".", 1)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        cmd = [hipcc()] + common + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = SAN_LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950"] + san + \
+          ["-shared-libsan", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose="-q" not in sys.argv)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose="-q" not in sys.argv)
+    else:
+        build(verbose="-q" not in sys.argv)
