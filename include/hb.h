@@ -257,11 +257,13 @@ typedef struct {
   int32_t precond;   /* HB_PREC_JACOBI (the paper's diag(P)) or HB_PREC_NODE_TIME    */
   double cfl_max;    /* cap of the pseudo step growth, dt <= cfl_max h_c / u_c
                         (<= 0: no cap beyond 1e6 times the initial step)        */
-  int32_t graphs;    /* 0: launch the kernels one by one; 1: when 4 N n <= 2^22
-                        and the Jv is HB_JV_EXACT, capture every Arnoldi step
-                        once as a HIP graph (kept with the mesh) and replay it.
-                        Results agree to rounding.  With graphs, report.jv_ms
-                        also includes the Gram-Schmidt work of each step.    */
+  int32_t graphs;    /* 0: launch the kernels one by one; 1: when 4 N n <= 2^22,
+                        the Jv is HB_JV_EXACT and the preconditioner is not
+                        HB_PREC_MEANFLOW, capture every Arnoldi step once as a
+                        HIP graph (kept with the mesh) and replay it (else the
+                        kernels are launched one by one).  Results agree to
+                        rounding.  With graphs, report.jv_ms also includes
+                        the Gram-Schmidt work of each step.                   */
   int32_t amg_sweeps; /* HB_PREC_MEANFLOW: Jacobi sweeps before and after each
                          coarse correction (0: 2)                               */
   int32_t amg_cycles; /* HB_PREC_MEANFLOW: V-cycles per application (0: 1)      */

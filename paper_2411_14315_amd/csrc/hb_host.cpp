@@ -1417,8 +1417,11 @@ int newton_run(hb_mesh* m, const hb_params* prm, const hb_bc* bc, double* Y,
   S.nblk = 1024;  // workgroups per vector slice of the Krylov reductions (upper bound)
   S.jv_kind = opts->jv_kind == HB_JV_PAPER ? HB_JV_PAPER : HB_JV_EXACT;
   S.jv64 = opts->precision == HB_F32_BASIS;
-  // on request, launch-bound sizes replay captured Arnoldi steps
-  S.use_graphs = opts->graphs == 1 && S.L <= ((int64_t)1 << 22) && S.jv_kind == HB_JV_EXACT;
+  // on request, launch-bound sizes replay captured Arnoldi steps (not with
+  // the mean-flow multigrid: its cycles take the pseudo-time coefficient by
+  // value, which a captured step would keep from the step it was captured in)
+  S.use_graphs = opts->graphs == 1 && S.L <= ((int64_t)1 << 22) && S.jv_kind == HB_JV_EXACT &&
+                 opts->precond != HB_PREC_MEANFLOW;
   const int N = S.N;
   const int64_t L = S.L;
   int rc = S.alloc();

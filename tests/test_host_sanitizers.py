@@ -88,7 +88,10 @@ def san_lib():
         pytest.skip("no clang to locate the AddressSanitizer runtime")
     if not os.path.exists(rt):
         pytest.skip("AddressSanitizer runtime not installed")
-    if not os.path.exists(build.SAN_LIB):
+    srcs = [os.path.join(build.CSRC, f) for f in build.SOURCES]
+    srcs += [os.path.join(build.CSRC, "hb_internal.h"), os.path.join(ROOT, "include", "hb.h")]
+    if (not os.path.exists(build.SAN_LIB) or
+            max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(build.SAN_LIB)):
         build.build_sanitized(verbose=False)
     return build.SAN_LIB, rt
 
