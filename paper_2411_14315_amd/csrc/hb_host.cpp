@@ -364,7 +364,11 @@ int ensure_precond(hb_mesh* m, int coarse_max, int pairwise, int N) {
   if (!m->pc || m->pc_coarse_max != coarse_max || m->pc_pairwise != pairwise) {
     hb::precond_destroy(m->pc);
     m->pc = nullptr;
-    HB_CHECK(hb::precond_create(m->dm.n, m->dm.ne, m->dm.tets, coarse_max, pairwise, &m->pc));
+    const hipError_t e = hb::precond_create(m->dm.n, m->dm.ne, m->dm.tets, coarse_max, pairwise,
+                                            &m->pc);
+    if (e == hipErrorInvalidValue)
+      return fail(HB_ERR_ARG, "the multigrid hierarchy does not coarsen below 2048 nodes");
+    HB_CHECK(e);
     m->pc_coarse_max = coarse_max;
     m->pc_pairwise = pairwise;
   }

@@ -58,6 +58,8 @@ enum {
 };
 // modes held in registers by the one-lane-per-node kernels
 constexpr int PC_MM = 12;
+// largest coarsest level (nodes) the dense per-mode inverse accepts
+constexpr int64_t kMaxCoarse = 2048;
 constexpr double QA_ = 0.58541019662496845446137605030969;
 constexpr double QB_ = 0.13819660112501051517954131656344;
 
@@ -1070,6 +1072,10 @@ hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int co
     g = std::move(gc);
   }
   const int64_t nc = pc->lv.back().n;
+  // the coarsest level is inverted densely per mode: refuse a hierarchy that
+  // stopped coarsening far above coarse_max (a graph of mostly isolated
+  // nodes) instead of allocating (K + 1) (4 nc)^2 complex values for it
+  if (nc > kMaxCoarse) return hipErrorInvalidValue;
   pc->dense_D = 4 * nc;
   if ((e = pc->flag.ensure(1))) return e;
   *out = pc.release();
