@@ -277,7 +277,8 @@ def test_learned_warm_start_gain(torch_gpu):
     trained on 384 solutions the solver generates (as corrections to the
     plain steady start) gives held-out starts closer to the root than the
     plain start, and Newton from them reaches the same root in fewer Newton
-    steps in total; the plain start is the fallback."""
+    steps in total; the plain start is the fallback.  A model of the whole
+    state does the same without a steady solve behind its guesses."""
     from hbinputs.problems import c4_stenosed, c4_stenosis_params
     from paper_2411_14315_amd import learned
     K, kw = 2, dict(n_rings=3, n_z=24, period=10.41)
@@ -307,3 +308,21 @@ def test_learned_warm_start_gain(torch_gpu):
     assert np.mean(err["learned"]) < 0.8 * np.mean(err["plain"])
     assert better >= 4
     assert newton["learned"] < newton["plain"]
+    # a model of the whole state (no steady solve behind the guess): every
+    # held-out draw converges from it, without fallback, to the same root in
+    # fewer Newton steps in total
+    whole = learned.WarmStart(rank=32, hidden=(128, 128), seed=0, target="solution").fit(
+        th_train, Y, steps=5000, lr=2e-3)
+    newton_w = {"plain": 0, "learned": 0}
+    for t in th_test:
+        case = learned.Case.build(c4_stenosed(t, K=K, **kw))
+        res = learned.compare_starts(whole, case, t)
+        p, l = res["plain"], res["learned"]
+        print("whole state", t[:2], "newton", p["newton_iters"], l["newton_iters"], "seconds",
+              p["start_s"] + p["wall_s"], l["start_s"] + l["wall_s"], l["used"], flush=True)
+        assert l["status"] == 0 and l["used"] == "learned"
+        assert res["solution_rel_diff"] <= 1e-5
+        newton_w["plain"] += p["newton_iters"]
+        newton_w["learned"] += l["newton_iters"]
+        case.mesh.close()
+    assert newton_w["learned"] < newton_w["plain"]
