@@ -376,6 +376,20 @@ int hb_outlet_flow(const hb_mesh* mesh, const hb_params* prm, const hb_bc* bc, c
 /* Node counts of the preconditioner's levels (finest first): sizes[0..max-1];
  * *n_levels = number of levels (0 before the hierarchy is built). */
 int hb_precond_levels(const hb_mesh* mesh, int64_t* sizes, int32_t max, int32_t* n_levels);
+/* The mean-flow multigrid's hierarchy of a mesh's node graph, built on the
+ * host alone (no device work; for checking it): tets (host [ne][4], 0-based,
+ * indices < n), aggregation 0 (two passes of pairwise matching) or 1 (a node
+ * with its free neighbours), coarsening until at most coarse_max (1..256)
+ * nodes remain or a level no longer shrinks by 10 %.  sizes (host
+ * [max_levels]) receives the node counts of the first max_levels levels,
+ * *n_levels the number of levels; agg0 (host [n] or NULL) the aggregate of
+ * each node of the finest level (-1 when there is one level); colour0 (host
+ * [n] or NULL) the colour class of each finest-level node (no two
+ * neighbours share one; the Gauss-Seidel smoother's classes).  HB_ERR_ARG
+ * for bad sizes, options or indices. */
+int hb_precond_hierarchy(int64_t n, int64_t ne, const int32_t* tets, int32_t coarse_max,
+                         int32_t aggregation, int32_t max_levels, int64_t* sizes,
+                         int32_t* n_levels, int32_t* agg0, int32_t* colour0);
 
 /* Per-stage timing of hb_residual / hb_jvp for profiling.  When enabled,
  * those calls record HIP events on their stream between stages:

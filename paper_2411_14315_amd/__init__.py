@@ -127,6 +127,7 @@ def load():
     lib.hb_precond_apply.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, dbl,
                                      C.POINTER(_PcOpts), i32, vp, vp, vp]
     lib.hb_precond_levels.argtypes = [vp, vp, i32, C.POINTER(i32)]
+    lib.hb_precond_hierarchy.argtypes = [i64, i64, vp, i32, i32, i32, vp, C.POINTER(i32), vp, vp]
     lib.hb_outlet_flow.argtypes = [vp, C.POINTER(_Params), C.POINTER(_BC), vp, vp, vp, vp]
     lib.hb_last_error.restype = C.c_char_p
     for name in ("hb_mesh_create", "hb_mesh_info", "hb_residual", "hb_jvp", "hb_jacobi",
@@ -135,7 +136,8 @@ def load():
                  "hb_mlp_forward_noalloc", "hb_mlp_loss_grad",
                  "hb_mlp_adam_step", "hb_pod_expand", "hb_pod_fit", "hb_sym_eig",
                  "hb_tm_residual", "hb_tm_jvp",
-                 "hb_tm_march", "hb_precond_apply", "hb_precond_levels", "hb_outlet_flow"):
+                 "hb_tm_march", "hb_precond_apply", "hb_precond_levels", "hb_outlet_flow",
+                 "hb_precond_hierarchy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -496,6 +498,24 @@ def precond_apply(mesh: Mesh, params, bc: BC, Y, X, shift: float = 0.0, op: str 
     _check(load().hb_precond_apply(mesh._h, C.byref(pc), C.byref(bcc), yp, float(shift),
                                    C.byref(o), op_, xp, outp, _stream(stream)))
     return OUT
+
+
+def precond_hierarchy(n_nodes: int, tets: np.ndarray, coarse_max: int = 24,
+                      aggregation: int = 0):
+    """The multigrid hierarchy of a mesh's node graph, built on the host
+    (hb_precond_hierarchy): (level sizes, aggregate of each fine node,
+    colour class of each fine node)."""
+    t = np.ascontiguousarray(tets, np.int32)
+    if t.ndim != 2 or t.shape[1] != 4:
+        raise HBError(HB_ERR_ARG, "tets must be (n_tets, 4)")
+    sizes = np.zeros(32, np.int64)
+    nl = C.c_int32()
+    agg = np.zeros(int(n_nodes), np.int32)
+    col = np.zeros(int(n_nodes), np.int32)
+    _check(load().hb_precond_hierarchy(int(n_nodes), t.shape[0], t.ctypes.data, int(coarse_max),
+                                       int(aggregation), 32, sizes.ctypes.data, C.byref(nl),
+                                       agg.ctypes.data, col.ctypes.data))
+    return [int(x) for x in sizes[:min(nl.value, 32)]], agg, col
 
 
 def precond_levels(mesh: Mesh) -> list:

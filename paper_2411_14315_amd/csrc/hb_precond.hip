@@ -37,10 +37,12 @@
 // are processed by every launch: the matrix
 // coefficients are read once per node pair and applied to the K+1 mode
 // vectors of the neighbour.
+#include "hb.h"
 #include "hb_internal.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <numeric>
 #include <memory>
@@ -1014,34 +1016,37 @@ hipError_t upload(DeviceArray<T>& d, const std::vector<T>& h) {
 
 }  // namespace
 
-hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int coarse_max,
-                          int pairwise, Precond** out) {
-  *out = nullptr;
-  std::vector<int32_t> T(4 * ne);
-  hipError_t e = hipMemcpy(T.data(), tets_dev, sizeof(int32_t) * 4 * ne, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return e;
-  std::unique_ptr<Precond> pc(new Precond());
-  HostGraph g = node_graph(n, ne, T);
-  T.clear();
-  T.shrink_to_fit();
+namespace {
+
+// One level of the hierarchy on the host: its node graph (CSR with self
+// loops, position of the diagonal), colour classes, and the transfer to the
+// next level (aggregate of each node, members of each aggregate, fine
+// entries of each coarse entry); the transfer is empty on the coarsest level.
+struct HostLevel {
+  int64_t n = 0, nnz = 0;
+  std::vector<int32_t> rowptr, col, diag, crows, agg, mptr, mem, gptr, gsrc;
+  std::vector<int64_t> cptr;
+};
+
+// The hierarchy of a mesh's node graph (tets SoA [4][ne], indices < n):
+// aggregation until at most coarse_max nodes remain or it stops coarsening.
+void build_levels(int64_t n, int64_t ne, const std::vector<int32_t>& tets_soa, int coarse_max,
+                  int pairwise, std::vector<HostLevel>& out) {
+  out.clear();
+  HostGraph g = node_graph(n, ne, tets_soa);
   for (int level = 0;; ++level) {
-    pc->lv.emplace_back();
-    PcLevel& L = pc->lv.back();
+    out.emplace_back();
+    HostLevel& L = out.back();
     const int64_t nl = (int64_t)g.rowptr.size() - 1;
     L.n = nl;
     L.nnz = g.rowptr[nl];
-    std::vector<int32_t> diag(nl);
+    L.diag.assign(nl, 0);
     for (int64_t i = 0; i < nl; ++i)
       for (int k = g.rowptr[i]; k < g.rowptr[i + 1]; ++k)
-        if (g.col[k] == i) diag[i] = k;
-    if ((e = upload(L.rowptr, g.rowptr)) || (e = upload(L.col, g.col)) || (e = upload(L.diag, diag)))
-      return e;
-    if ((e = L.val.ensure((size_t)L.nnz * PC_NF))) return e;
-    {
-      std::vector<int32_t> rows;
-      colour_classes(g, L.cptr, rows);
-      if ((e = upload(L.crows, rows))) return e;
-    }
+        if (g.col[k] == i) L.diag[i] = k;
+    colour_classes(g, L.cptr, L.crows);
+    L.rowptr = g.rowptr;
+    L.col = g.col;
     if (nl <= coarse_max || level >= 15) break;
     std::vector<int32_t> agg, mptr, mem;
     const int64_t na = pairwise ? aggregate_pairs(g, agg) : aggregate(g, agg);
@@ -1066,16 +1071,48 @@ hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int co
       std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
       for (int64_t k = 0; k < L.nnz; ++k) gsrc[fill[cmap[k]]++] = (int32_t)k;
     }
-    if ((e = upload(L.agg, agg)) || (e = upload(L.mptr, mptr)) || (e = upload(L.mem, mem)) ||
-        (e = upload(L.gptr, gptr)) || (e = upload(L.gsrc, gsrc)))
-      return e;
+    L.agg = std::move(agg);
+    L.mptr = std::move(mptr);
+    L.mem = std::move(mem);
+    L.gptr = std::move(gptr);
+    L.gsrc = std::move(gsrc);
     g = std::move(gc);
   }
-  const int64_t nc = pc->lv.back().n;
+}
+
+}  // namespace
+
+hipError_t precond_create(int64_t n, int64_t ne, const int32_t* tets_dev, int coarse_max,
+                          int pairwise, Precond** out) {
+  *out = nullptr;
+  std::vector<int32_t> T(4 * ne);
+  hipError_t e = hipMemcpy(T.data(), tets_dev, sizeof(int32_t) * 4 * ne, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  std::vector<HostLevel> hl;
+  build_levels(n, ne, T, coarse_max, pairwise, hl);
+  T.clear();
+  T.shrink_to_fit();
+  const int64_t nc = hl.back().n;
   // the coarsest level is inverted densely per mode: refuse a hierarchy that
   // stopped coarsening far above coarse_max (a graph of mostly isolated
   // nodes) instead of allocating (K + 1) (4 nc)^2 complex values for it
   if (nc > kMaxCoarse) return hipErrorInvalidValue;
+  std::unique_ptr<Precond> pc(new Precond());
+  for (auto& H : hl) {
+    pc->lv.emplace_back();
+    PcLevel& L = pc->lv.back();
+    L.n = H.n;
+    L.nnz = H.nnz;
+    if ((e = upload(L.rowptr, H.rowptr)) || (e = upload(L.col, H.col)) ||
+        (e = upload(L.diag, H.diag)) || (e = upload(L.crows, H.crows)))
+      return e;
+    L.cptr = H.cptr;
+    if ((e = L.val.ensure((size_t)L.nnz * PC_NF))) return e;
+    if (!H.agg.empty() &&
+        ((e = upload(L.agg, H.agg)) || (e = upload(L.mptr, H.mptr)) || (e = upload(L.mem, H.mem)) ||
+         (e = upload(L.gptr, H.gptr)) || (e = upload(L.gsrc, H.gsrc))))
+      return e;
+  }
   pc->dense_D = 4 * nc;
   if ((e = pc->flag.ensure(1))) return e;
   *out = pc.release();
@@ -1298,3 +1335,35 @@ template hipError_t precond_matvec<double, double>(Precond*, int64_t, const doub
                                                    double*, hipStream_t);
 
 }  // namespace hb
+
+extern "C" int hb_precond_hierarchy(int64_t n, int64_t ne, const int32_t* tets, int32_t coarse_max,
+                                    int32_t aggregation, int32_t max_levels, int64_t* sizes,
+                                    int32_t* n_levels, int32_t* agg0, int32_t* colour0) {
+  auto fail = [](const char* msg) {
+    hb::set_last_error(msg);
+    return (int)HB_ERR_ARG;
+  };
+  if (n < 1 || ne < 1 || !tets || !sizes || !n_levels || max_levels < 1)
+    return fail("bad argument");
+  if (n > INT32_MAX || coarse_max < 1 || coarse_max > 256 || (aggregation != 0 && aggregation != 1))
+    return fail("bad hierarchy options");
+  std::vector<int32_t> soa(4 * (size_t)ne);
+  for (int64_t t = 0; t < ne; ++t)
+    for (int A = 0; A < 4; ++A) {
+      const int32_t v = tets[4 * t + A];
+      if (v < 0 || v >= n) return fail("tetrahedron node index out of range");
+      soa[(size_t)A * ne + t] = v;
+    }
+  std::vector<hb::HostLevel> hl;
+  hb::build_levels(n, ne, soa, coarse_max, aggregation == 0, hl);
+  *n_levels = (int32_t)hl.size();
+  for (int32_t l = 0; l < max_levels && l < (int32_t)hl.size(); ++l) sizes[l] = hl[l].n;
+  if (agg0)
+    for (int64_t i = 0; i < n; ++i) agg0[i] = hl[0].agg.empty() ? -1 : hl[0].agg[i];
+  if (colour0) {
+    const auto& L = hl[0];
+    for (size_t c = 0; c + 1 < L.cptr.size(); ++c)
+      for (int64_t k = L.cptr[c]; k < L.cptr[c + 1]; ++k) colour0[L.crows[k]] = (int32_t)c;
+  }
+  return HB_OK;
+}

@@ -6,7 +6,9 @@ their normal and error paths: the symmetric eigensolver at several sizes
 (including repeated eigenvalues and n = 1), mesh creation with out-of-range
 indices, degenerate tetrahedra, a missing outlet group and NULL arrays, and
 NULL or out-of-range arguments to the solver, preconditioner, POD and
-network entry points.  Any sanitizer report fails the test."""
+network entry points, and the multigrid hierarchy's graph code (matching,
+aggregation, colouring) on a cube mesh.  Any sanitizer report fails the
+test."""
 import os
 import subprocess
 import sys
@@ -75,6 +77,19 @@ CHILD = textwrap.dedent(r"""
     lib.hb_pod_expand.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp]
     assert lib.hb_pod_expand(0, 0, None, None, None, None, None, None) == -1
     assert len(lib.hb_last_error()) > 0
+    lib.hb_precond_hierarchy.argtypes = [i64, i64, vp, i32, i32, i32, vp, C.POINTER(i32), vp, vp]
+    mc = cube_mesh(4)
+    tets = np.ascontiguousarray(mc.tets, np.int32)
+    for aggr in (0, 1):
+        sizes = np.zeros(8, np.int64); nl = i32()
+        agg = np.zeros(mc.n_nodes, np.int32); col = np.zeros(mc.n_nodes, np.int32)
+        assert lib.hb_precond_hierarchy(mc.n_nodes, tets.shape[0], tets.ctypes.data, 8, aggr, 8,
+                                        sizes.ctypes.data, C.byref(nl), agg.ctypes.data,
+                                        col.ctypes.data) == 0
+        assert nl.value >= 2 and sizes[0] == mc.n_nodes
+    bad = tets.copy(); bad[1, 2] = mc.n_nodes
+    assert lib.hb_precond_hierarchy(mc.n_nodes, bad.shape[0], bad.ctypes.data, 8, 0, 8,
+                                    sizes.ctypes.data, C.byref(nl), None, None) == -1
     print("host entry points clean", flush=True)
 """)
 
